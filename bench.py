@@ -1,0 +1,277 @@
+"""Benchmark of the differentiable Poisson solver on one MI355X.
+
+A step is one forward + backward solve (every stage of the hot path: binning,
+splat + r2c, the axis FFT passes, the fused spectral operator, c2r + gather,
+the FP64 reductions, normalisation, and the whole adjoint) over one resident
+synthetic oriented point cloud. Inputs, the loss gradient and all buffers are
+in HBM before the timed region starts.
+
+Default workload: 256^3 grid, 100,000 points on a random superellipsoid
+(seed 2), normals perturbed by N(0, 0.05^2) and renormalised, sigma = 2 cells;
+the loss is mean((chi - chi_t)^2) with chi_t from the clean normals.
+
+Printed: ONE JSON line with solves/s, the dominant kernel's roofline
+(algorithmic bytes / HIP-event duration, against 8 TB/s), the whole-step
+roofline, secondary 128^3 and forward-only rates, and the FP64 oracle timed on
+the host's cores on one solve of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PSR fwd+bwd solves/sec at 128^3/256^3 + %HBM roofline; p50/p99 latency in serving"
+HBM_PEAK_GBS = 8000.0
+
+
+# --------------------------------------------------------------------------- byte model
+def half_spec_bytes(r: int) -> int:
+    """One complex64 half-spectrum channel: r * r * (r/2 + 1) * 8 bytes."""
+    return r * r * (r // 2 + 1) * 8
+
+
+def stage_bytes(r: int, P: int) -> dict:
+    """Algorithmic bytes per launch of each stage: every array the stage must
+    read once and write once (points, spectra, grids), nothing counted twice."""
+    S = half_spec_bytes(r)
+    N4 = 4 * r ** 3
+    return {
+        "bin": 24 * P + 32 * P * 2 + 8 * P,
+        "P1_splat_r2c": 32 * P + 3 * S,
+        "P2_fft_j1": 6 * S,
+        "P3_fft_j0_spectral_ifft_j0": 3 * S + S,
+        "P4_ifft_j1": 2 * S,
+        "P5_c2r_gather": S + N4 + 32 * P + 64 * P,
+        "fwd_reduce": 64 * P + 16 * P,
+        "normalize": 2 * N4,
+        "bwd_reduce": 2 * N4,
+        "B1_cotangent_r2c": N4 + 32 * P + S,
+        "B2_fft_j1": 2 * S,
+        "B3_fft_j0_conjop_ifft_j0": S + 3 * S,
+        "B4_ifft_j1": 6 * S,
+        "B5_c2r_gather": 3 * S + 32 * P + 128 * P,
+        "bwd_finalize": 128 * P + 16 * P + 32 * P + 24 * P,
+    }
+
+
+def b_stage(r: int, P: int) -> int:
+    """Whole-step algorithmic bytes of forward+backward: 128 r^3 + 72 P (every
+    named array written once and read once in FP32; each 3D transform one
+    read + one write)."""
+    return 128 * r ** 3 + 72 * P
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2106_03452_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_stage: str, workload: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_" + workload + ".json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    st = d.get("stages", {}).get(kernel_stage)
+    if not st:
+        return None
+    return st.get("hbm_bytes_per_launch")
+
+
+# --------------------------------------------------------------------------- CPU baseline
+CPU_SNIPPET = r"""
+import json, os, sys, time
+sys.path.insert(0, {root!r})
+import numpy as np
+import oracle, psr_synth as S
+sh = S.config_c3()
+chi_t, _ = oracle.forward(sh.points_clean, sh.normals_clean, sh.res, sh.sigma)
+t0 = time.perf_counter()
+chi, aux = oracle.forward(sh.points, sh.normals, sh.res, sh.sigma)
+G = 2.0 * (chi - chi_t) / chi.size
+dc, dn = oracle.backward(aux, G)
+t1 = time.perf_counter()
+print(json.dumps(dict(seconds=t1 - t0)))
+"""
+
+
+def cpu_baseline():
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               NUMEXPR_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", CPU_SNIPPET.format(root=ROOT)], env=env, capture_output=True,
+                         text=True, timeout=900)
+    if out.returncode != 0:
+        sys.stderr.write(out.stderr[-2000:])
+        return None
+    sec = json.loads(out.stdout.strip().splitlines()[-1])["seconds"]
+    return {"value": round(1.0 / sec, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full forward+backward solve of the same 256^3 / 100k-point workload "
+                      f"(FP64 NumPy oracle, single thread, {sec:.1f} s; loss target chi_t computed "
+                      f"outside the timed sample)"}
+
+
+# --------------------------------------------------------------------------- GPU runs
+def prepare(shape, dev, torch, F):
+    pts = torch.from_numpy(shape.points).to(dev)
+    nrm = torch.from_numpy(shape.normals).to(dev)
+    r, P = shape.res, shape.P
+    chi_t, _ = F.forward(torch.from_numpy(shape.points_clean).to(dev), torch.from_numpy(shape.normals_clean).to(dev),
+                         r, shape.sigma)
+    chi, saved = F.forward(pts, nrm, r, shape.sigma)
+    G = (2.0 * (chi - chi_t) / chi.numel()).contiguous()
+    from paper_2106_03452_amd import _lib
+    ws = torch.empty(_lib.workspace_bytes(r, P), dtype=torch.uint8, device=dev)
+    dp = torch.empty((P, 3), dtype=torch.float32, device=dev)
+    dn = torch.empty((P, 3), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    return dict(pts=pts, nrm=nrm, chi=chi, saved=saved, G=G, ws=ws, dp=dp, dn=dn, r=r, P=P, sigma=shape.sigma)
+
+
+def make_step(b, ctx, backward: bool = True):
+    import ctypes
+    import torch
+    from paper_2106_03452_amd import _lib
+    L = _lib.lib()
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    wsb = ctypes.c_size_t(b["ws"].numel())
+    args_f = (ctx.handle, p(b["pts"]), p(b["nrm"]), b["P"], b["r"], b["sigma"], p(b["chi"]), p(b["saved"]),
+              p(b["ws"]), wsb, stream)
+    args_b = (ctx.handle, b["P"], b["r"], b["sigma"], p(b["chi"]), p(b["saved"]), p(b["G"]), p(b["dp"]),
+              p(b["dn"]), p(b["ws"]), wsb, stream)
+
+    def step():
+        rc = L.psr_forward(*args_f)
+        if rc:
+            raise RuntimeError(f"psr_forward failed: {rc}")
+        if backward:
+            rc = L.psr_backward(*args_b)
+            if rc:
+                raise RuntimeError(f"psr_backward failed: {rc}")
+    return step
+
+
+def timed(step, steps, warmup, torch):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 128^3 and forward-only lines")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the solver runs on a single MI355X (its multi-GPU slab "
+              "decomposition is a design, not part of this build). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import psr_synth as S
+    from paper_2106_03452_amd import _lib
+    from paper_2106_03452_amd import function as F
+
+    dev = torch.device("cuda", 0)
+    ctx = _lib.context(0)
+    shape = S.config_c3()
+    b = prepare(shape, dev, torch, F)
+    r, P = b["r"], b["P"]
+
+    # main timed region: forward + backward, no per-kernel events
+    step = make_step(b, ctx)
+    dt = timed(step, args.steps, args.warmup, torch)
+    ms = dt / args.steps * 1e3
+    value = args.steps / dt
+
+    # per-stage durations (HIP events on the solve stream) to find the dominant kernel
+    ctx.set("timers", 1)
+    ctx.reset_timers()
+    timed(step, max(5, args.steps // 3), 1, torch)
+    times = ctx.stage_times()
+    per_launch = {k: (v[0] / v[1]) for k, v in times.items() if v[1] > 0}
+    dom = max(per_launch, key=lambda k: per_launch[k])
+    # time the dominant kernel alone inside a timed region identical to the main one
+    names = [_lib.lib().psr_stage_name(i).decode() for i in range(_lib.lib().psr_num_stages())]
+    ctx.set("timer_mask", 1 << names.index(dom))
+    ctx.reset_timers()
+    dt2 = timed(step, args.steps, 1, torch)
+    t_dom = ctx.stage_times()[dom]
+    ctx.set("timers", 0)
+    dom_ms = t_dom[0] / t_dom[1]
+    sb = stage_bytes(r, P)
+    achieved = sb[dom] / (dom_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(dom, "c3_256")
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": dom, "algorithmic_bytes_per_launch": sb[dom], "avg_launch_ms": round(dom_ms, 5)}
+    step_bytes = b_stage(r, P)
+    step_roof = {"bytes": step_bytes, "achieved_GBs": round(step_bytes / (ms * 1e-3) / 1e9, 1),
+                 "frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "model": "B_stage = 128 r^3 + 72 P (fwd+bwd)"}
+    breakdown = {k: round(v, 4) for k, v in sorted(per_launch.items(), key=lambda kv: -kv[1])}
+
+    secondary = {}
+    if not args.no_secondary:
+        fwd = make_step(b, ctx, backward=False)
+        dtf = timed(fwd, args.steps, 2, torch)
+        secondary["fwd_only_256"] = {"solves_per_s": round(args.steps / dtf, 2), "ms": round(dtf / args.steps * 1e3, 4),
+                                     "paper_gtx1080ti_ms": 140.0}
+        sh2 = S.config_c2()
+        b2 = prepare(sh2, dev, torch, F)
+        s2 = make_step(b2, ctx)
+        d2 = timed(s2, args.steps * 3, args.warmup, torch)
+        ms2 = d2 / (args.steps * 3) * 1e3
+        secondary["fwd_bwd_128"] = {"solves_per_s": round(args.steps * 3 / d2, 2), "ms": round(ms2, 4),
+                                    "step_roofline_frac": round(b_stage(128, sh2.P) / (ms2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                    "workload": "128^3, 20k points torus+sphere, sigma 2"}
+        f2 = make_step(b2, ctx, backward=False)
+        d3 = timed(f2, args.steps * 3, 2, torch)
+        secondary["fwd_only_128"] = {"solves_per_s": round(args.steps * 3 / d3, 2),
+                                     "ms": round(d3 / (args.steps * 3) * 1e3, 4), "paper_gtx1080ti_ms": 12.0}
+        del b2
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "fwd+bwd 256^3, 100k points on a superellipsoid (seed 2), noisy normals, sigma 2",
+                   "res": r, "npoints": P, "sigma": shape.sigma, "precision": "FP32 grid, FP64 reductions",
+                   "parallelism": "single GPU"},
+        "roofline": roof, "step_roofline": step_roof, "stage_ms": breakdown,
+        "dominant_kernel_region_ms_per_step": round(dt2 / args.steps * 1e3, 4),
+        "secondary": secondary, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * psr.h -- C ABI of the MI355X (gfx950) differentiable Poisson solver.
+ *
+ * The library computes the indicator grid of Peng et al., "Shape As Points: A
+ * Differentiable Poisson Solver" (NeurIPS 2021) from an oriented point cloud,
+ * and the exact adjoint of that computation:
+ *
+ *   splat        v_d[j] = sum_i T(c_i, j/r, 1/r) n_{i,d}        (supplement Sec. A.1)
+ *   solve        chi'   = IFFT( g(u) * i u.FFT(v) / (-2 pi |u|^2) )   (main Eq. 3)
+ *   normalise    chi    = m / |c| * (chi' - mean_i chi'(c_i))        (main Eq. 4,
+ *                         with the constraint of main Eq. 2, m = 0.5)
+ *
+ * Conventions (the paper leaves them open; the library and its reference agree):
+ *   - periodic grid on [0,1)^3 with r vertices per axis, vertex j at j/r; point
+ *     coordinates are taken mod 1; corner indices wrap mod r;
+ *   - grid layout X[j0][j1][j2], row-major, j2 fastest; point column a maps to
+ *     grid axis a;
+ *   - u is the integer wavenumber (k for k < r/2, else k - r), sigma is in grid
+ *     cells; the odd derivative factor is 0 at the Nyquist index r/2 while
+ *     |u|^2 keeps (r/2)^2; chi~(0) = 0;
+ *   - scale reading "B" (default): c = chi'(0,0,0) - mean, so |chi(0,0,0)| = m
+ *     exactly as main Eq. 2 requires; reading "A" uses c = chi'(0,0,0) as main
+ *     Eq. 4 is printed;
+ *   - normals are used as given, never renormalised (supplement, outlier
+ *     handling: small normals mute outliers).
+ *
+ * Precision: the grid work (splat, FFTs, spectral operator, gather) runs in
+ * FP32 with FP32 accumulation; the mean of chi' at the points, the scale and
+ * the backward reductions sum G and sum G*chi are accumulated in FP64.
+ *
+ * Memory: every pointer argument is DEVICE memory owned by the caller unless
+ * stated otherwise. The library allocates nothing per call: grid-sized scratch
+ * comes in through `workspace` (size from psr_workspace_bytes) and the
+ * per-solve state that backward needs lives in `saved` (size from
+ * psr_saved_bytes). Buffers must be 256-byte aligned.
+ *
+ * Asynchrony: psr_forward, psr_backward and psr_run_batched only enqueue
+ * kernels on `stream` and return. Argument errors are reported at once and
+ * nothing is launched. Data-dependent errors (non-finite coordinates, a zero
+ * or non-finite scale) are written to a status word inside `saved`, read with
+ * psr_saved_status (which synchronises the stream); the grid is then NaN.
+ */
+#ifndef PSR_H
+#define PSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes returned by every entry point (0 = success). */
+enum {
+  PSR_OK = 0,
+  PSR_EINVAL = -1,        /* bad argument: NULL pointer, npoints < 1, res not a power of two in
+                             [8, 512], sigma negative or non-finite, workspace too small, bad key */
+  PSR_ENOMEM = -2,        /* device allocation failed (context creation only) */
+  PSR_EDEGENERATE = -3,   /* scale c is zero or non-finite (e.g. all normals zero); chi is NaN */
+  PSR_EDEVICE = -4,       /* a HIP runtime call failed */
+  PSR_ENOTREADY = -5,     /* reserved */
+  PSR_ENONFINITE = -6     /* a point coordinate is NaN or Inf; chi is NaN */
+};
+
+#define PSR_MIN_RES 8
+#define PSR_MAX_RES 512
+
+typedef struct psr_ctx psr_ctx;
+
+/* Library version, major*10000 + minor*100 + patch. */
+int psr_version(void);
+
+/* Human-readable text for a status code. Never NULL; the string is static. */
+const char* psr_strerror(int code);
+
+/* Create a context on HIP device `device`: uploads the FP64-built twiddle
+ * tables and sets defaults (m = 0.5, reading B, timers off).
+ * Returns PSR_EINVAL for a bad device, PSR_ENOMEM / PSR_EDEVICE on failure. */
+int psr_ctx_create(psr_ctx** out, int device);
+int psr_ctx_destroy(psr_ctx* ctx);
+
+/* Options: "m" (target magnitude at the origin, > 0, default 0.5),
+ * "reading" (0 = B, default; 1 = A), "timers" (0/1: per-stage HIP-event timing),
+ * "timer_mask" (bit s set = time stage s; needs timers on; default all). */
+int psr_ctx_set(psr_ctx* ctx, const char* key, double value);
+int psr_ctx_get(const psr_ctx* ctx, const char* key, double* value);
+
+/* Host-only size queries (no device calls). `with_backward` is accepted for
+ * symmetry; forward and backward use the same workspace layout. */
+int psr_workspace_bytes(int res, int64_t npoints, int with_backward, size_t* bytes);
+int psr_saved_bytes(int res, int64_t npoints, size_t* bytes);
+
+/* Forward solve (main Eqs. 2-4).
+ *   points, normals : [npoints][3] float32, row-major. Not modified; must stay
+ *                     unchanged until backward if backward is called.
+ *   res             : grid vertices per axis, power of two in [8, 512].
+ *   sigma           : Gaussian bandwidth in grid cells (main Eq. 3), >= 0.
+ *   chi             : [res][res][res] float32 output (written in full).
+ *   saved           : psr_saved_bytes(res, npoints) bytes; receives the sorted
+ *                     points, the scalars mean/c/scale/chi'(0) and the status.
+ *   workspace       : at least psr_workspace_bytes(res, npoints, .) bytes.
+ * The call is stream-ordered and asynchronous. */
+int psr_forward(psr_ctx* ctx, const float* points, const float* normals, int64_t npoints,
+                int res, float sigma, float* chi, void* saved, void* workspace,
+                size_t workspace_bytes, hipStream_t stream);
+
+/* Backward (adjoint) of psr_forward: given dchi = dL/dchi, writes
+ * dpoints = dL/dpoints and dnormals = dL/dnormals ([npoints][3] float32; either
+ * may be NULL to skip it). `chi` is the forward's output and `saved` its state,
+ * both unchanged since the forward; npoints/res/sigma must repeat the forward's.
+ * The derivative of the position wrap (mod 1) is taken as 1; on a cell face the
+ * derivative is the one of the cell above (right derivative). */
+int psr_backward(psr_ctx* ctx, int64_t npoints, int res, float sigma, const float* chi,
+                 const void* saved, const float* dchi, float* dpoints, float* dnormals,
+                 void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Synchronises `stream`, then reads the status word written by the forward
+ * on that stream into *status (PSR_OK, PSR_EDEGENERATE or PSR_ENONFINITE). */
+int psr_saved_status(const void* saved, hipStream_t stream, int* status);
+
+/* Synchronises `stream`, then reads the forward's FP64 scalars: the mean of
+ * chi' at the points, the scale denominator c, the scale m/|c| and chi'(0,0,0).
+ * Any output pointer may be NULL. */
+int psr_saved_scalars(const void* saved, hipStream_t stream, double* mean, double* cscale,
+                      double* scale, double* chi0);
+
+/* One solve of a batch. Inputs/outputs as in psr_forward/psr_backward.
+ * `dchi` NULL = forward only; otherwise the backward runs right after the
+ * forward and writes dpoints/dnormals (either may be NULL). `workspace` and
+ * `saved` are per job and must not overlap between jobs. `status` is unused
+ * by the library (kept for callers). */
+typedef struct psr_job {
+  const float* points;
+  const float* normals;
+  int64_t npoints;
+  int res;
+  float sigma;
+  float* chi;
+  void* saved;
+  const float* dchi;
+  float* dpoints;
+  float* dnormals;
+  void* workspace;
+  size_t workspace_bytes;
+} psr_job;
+
+/* Run `njobs` independent solves with one launch per pipeline stage for the
+ * whole batch (jobs may mix resolutions and point counts). Stream-ordered. */
+int psr_run_batched(psr_ctx* ctx, int njobs, const psr_job* jobs, hipStream_t stream);
+
+/* Test hooks. psr_debug_spectral runs only the spectral solve on a given
+ * field v ([3][res^3] float32) and writes the unnormalised chi' ([res^3]).
+ * psr_debug_splat writes the rasterised field v ([3][res^3]) for the points;
+ * `saved` and `workspace` as for psr_forward. */
+int psr_debug_spectral(psr_ctx* ctx, const float* v, int res, float sigma, float* chi_prime,
+                       void* workspace, size_t workspace_bytes, hipStream_t stream);
+int psr_debug_splat(psr_ctx* ctx, const float* points, const float* normals, int64_t npoints,
+                    int res, float* v, void* saved, void* workspace, size_t workspace_bytes,
+                    hipStream_t stream);
+
+/* Stage timers (enabled with psr_ctx_set(ctx, "timers", 1)). Synchronises all
+ * recorded events and returns, per stage id in [0, n), the summed duration in
+ * milliseconds and the number of launches timed; psr_stage_name gives the id's
+ * name. psr_ctx_reset_timers clears the sums. */
+int psr_ctx_stage_times(psr_ctx* ctx, double* ms, int64_t* counts, int n);
+int psr_ctx_reset_timers(psr_ctx* ctx);
+const char* psr_stage_name(int stage);
+int psr_num_stages(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSR_H */

@@ -1,0 +1,374 @@
+// C ABI of the solver library: argument checking, context (twiddle tables,
+// options, stage timers), workspace and saved-state layout, dispatch to the
+// per-resolution launch sequences.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "psr.h"
+#include "psr_internal.h"
+
+namespace psr {
+
+struct cf {
+  float x, y;
+};
+
+struct Timers {
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t open[NUM_STAGES] = {};
+  double ms[NUM_STAGES] = {};
+  int64_t cnt[NUM_STAGES] = {};
+  uint32_t mask = 0xffffffffu;  // stages to time
+
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void flush() {
+    for (auto& r : pending) {
+      float t = 0.0f;
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        ms[r.stage] += t;
+        cnt[r.stage] += 1;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+  ~Timers() {
+    flush();
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+void timer_begin(Timers* t, int stage, hipStream_t s) {
+  if (!((t->mask >> stage) & 1u)) return;
+  hipEvent_t e = t->get();
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  t->open[stage] = e;
+}
+
+void timer_end(Timers* t, int stage, hipStream_t s) {
+  hipEvent_t a = t->open[stage];
+  if (!a) return;
+  hipEvent_t b = t->get();
+  if (!b) return;
+  (void)hipEventRecord(b, s);
+  t->open[stage] = nullptr;
+  t->pending.push_back({stage, a, b});
+  if (t->pending.size() > 8192) t->flush();
+}
+
+}  // namespace psr
+
+struct psr_ctx {
+  int device = 0;
+  psr::cf* tw = nullptr;
+  double m = 0.5;
+  int reading = 0;
+  psr::Timers* timers = nullptr;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+bool valid_res(int res) {
+  return res >= PSR_MIN_RES && res <= PSR_MAX_RES && (res & (res - 1)) == 0;
+}
+
+bool valid_P(int64_t P) { return P >= 1 && P <= ((int64_t)1 << 30); }
+
+bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
+psr::Exec make_exec(psr_ctx* ctx, float sigma, hipStream_t stream) {
+  psr::Exec x;
+  x.stream = stream;
+  x.tw = ctx->tw;
+  x.sigma = sigma;
+  x.m = ctx->m;
+  x.reading = ctx->reading;
+  x.timers = ctx->timers;
+  return x;
+}
+
+const char* const kStageNames[psr::NUM_STAGES] = {
+    "bin", "P1_splat_r2c", "P2_fft_j1", "P3_fft_j0_spectral_ifft_j0", "P4_ifft_j1", "P5_c2r_gather",
+    "fwd_reduce", "normalize", "bwd_reduce", "B1_cotangent_r2c", "B2_fft_j1", "B3_fft_j0_conjop_ifft_j0",
+    "B4_ifft_j1", "B5_c2r_gather", "bwd_finalize"};
+
+}  // namespace
+
+extern "C" {
+
+int psr_version(void) { return 10000; }
+
+const char* psr_strerror(int code) {
+  switch (code) {
+    case PSR_OK: return "ok";
+    case PSR_EINVAL: return "invalid argument";
+    case PSR_ENOMEM: return "out of device memory";
+    case PSR_EDEGENERATE: return "degenerate scale: chi'(0) - mean is zero or non-finite";
+    case PSR_EDEVICE: return "HIP runtime error";
+    case PSR_ENOTREADY: return "not ready";
+    case PSR_ENONFINITE: return "non-finite point coordinate";
+    default: return "unknown status code";
+  }
+}
+
+int psr_ctx_create(psr_ctx** out, int device) {
+  if (!out) return PSR_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess) return PSR_EDEVICE;
+  if (device < 0 || device >= ndev) return PSR_EINVAL;
+  DeviceGuard g(device);
+  psr_ctx* c = new (std::nothrow) psr_ctx();
+  if (!c) return PSR_ENOMEM;
+  c->device = device;
+  // twiddle tables exp(-2 pi i e / L), e in [0, L), built in FP64, for L = 2..1024
+  const int total = 2048;
+  std::vector<psr::cf> host(total, psr::cf{0.0f, 0.0f});
+  for (int L = 2; L <= 1024; L *= 2) {
+    for (int e = 0; e < L; ++e) {
+      const double a = -2.0 * M_PI * (double)e / (double)L;
+      host[L + e] = psr::cf{(float)std::cos(a), (float)std::sin(a)};
+    }
+  }
+  if (hipMalloc(&c->tw, total * sizeof(psr::cf)) != hipSuccess) {
+    delete c;
+    return PSR_ENOMEM;
+  }
+  if (hipMemcpy(c->tw, host.data(), total * sizeof(psr::cf), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(c->tw);
+    delete c;
+    return PSR_EDEVICE;
+  }
+  *out = c;
+  return PSR_OK;
+}
+
+int psr_ctx_destroy(psr_ctx* ctx) {
+  if (!ctx) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  delete ctx->timers;
+  if (ctx->tw) (void)hipFree(ctx->tw);
+  delete ctx;
+  return PSR_OK;
+}
+
+int psr_ctx_set(psr_ctx* ctx, const char* key, double value) {
+  if (!ctx || !key) return PSR_EINVAL;
+  if (!std::strcmp(key, "m")) {
+    if (!(value > 0.0) || !std::isfinite(value)) return PSR_EINVAL;
+    ctx->m = value;
+    return PSR_OK;
+  }
+  if (!std::strcmp(key, "reading")) {
+    if (value != 0.0 && value != 1.0) return PSR_EINVAL;
+    ctx->reading = (int)value;
+    return PSR_OK;
+  }
+  if (!std::strcmp(key, "timers")) {
+    if (value != 0.0 && value != 1.0) return PSR_EINVAL;
+    DeviceGuard g(ctx->device);
+    if (value == 1.0 && !ctx->timers) {
+      ctx->timers = new (std::nothrow) psr::Timers();
+      if (!ctx->timers) return PSR_ENOMEM;
+    }
+    if (value == 0.0 && ctx->timers) {
+      delete ctx->timers;
+      ctx->timers = nullptr;
+    }
+    return PSR_OK;
+  }
+  if (!std::strcmp(key, "timer_mask")) {
+    if (!ctx->timers || !(value >= 0.0) || value > 4294967295.0 || value != std::floor(value)) return PSR_EINVAL;
+    ctx->timers->mask = (uint32_t)value;
+    return PSR_OK;
+  }
+  return PSR_EINVAL;
+}
+
+int psr_ctx_get(const psr_ctx* ctx, const char* key, double* value) {
+  if (!ctx || !key || !value) return PSR_EINVAL;
+  if (!std::strcmp(key, "m")) *value = ctx->m;
+  else if (!std::strcmp(key, "reading")) *value = ctx->reading;
+  else if (!std::strcmp(key, "timers")) *value = ctx->timers ? 1.0 : 0.0;
+  else if (!std::strcmp(key, "device")) *value = ctx->device;
+  else if (!std::strcmp(key, "timer_mask")) *value = ctx->timers ? (double)ctx->timers->mask : 0.0;
+  else return PSR_EINVAL;
+  return PSR_OK;
+}
+
+int psr_workspace_bytes(int res, int64_t npoints, int with_backward, size_t* bytes) {
+  (void)with_backward;
+  if (!bytes || !valid_res(res) || !valid_P(npoints)) return PSR_EINVAL;
+  *bytes = psr::ws_layout(res, npoints).total;
+  return PSR_OK;
+}
+
+int psr_saved_bytes(int res, int64_t npoints, size_t* bytes) {
+  if (!bytes || !valid_res(res) || !valid_P(npoints)) return PSR_EINVAL;
+  *bytes = psr::saved_layout(res, npoints).total;
+  return PSR_OK;
+}
+
+int psr_forward(psr_ctx* ctx, const float* points, const float* normals, int64_t npoints, int res, float sigma,
+                float* chi, void* saved, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!ctx || !points || !normals || !chi || !saved || !workspace) return PSR_EINVAL;
+  if (!valid_res(res) || !valid_P(npoints) || !(sigma >= 0.0f) || !std::isfinite(sigma)) return PSR_EINVAL;
+  if (!aligned(saved, 256) || !aligned(workspace, 256) || !aligned(chi, 16)) return PSR_EINVAL;
+  const psr::WsLayout L = psr::ws_layout(res, npoints);
+  if (workspace_bytes < L.total) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  psr::Exec x = make_exec(ctx, sigma, stream);
+  return psr::run_forward(x, res, points, normals, npoints, chi, psr::ws_view(workspace, L),
+                          psr::saved_view(saved, psr::saved_layout(res, npoints)));
+}
+
+int psr_backward(psr_ctx* ctx, int64_t npoints, int res, float sigma, const float* chi, const void* saved,
+                 const float* dchi, float* dpoints, float* dnormals, void* workspace, size_t workspace_bytes,
+                 hipStream_t stream) {
+  if (!ctx || !chi || !saved || !dchi || !workspace) return PSR_EINVAL;
+  if (!valid_res(res) || !valid_P(npoints) || !(sigma >= 0.0f) || !std::isfinite(sigma)) return PSR_EINVAL;
+  if (!aligned(saved, 256) || !aligned(workspace, 256) || !aligned(chi, 16) || !aligned(dchi, 16))
+    return PSR_EINVAL;
+  const psr::WsLayout L = psr::ws_layout(res, npoints);
+  if (workspace_bytes < L.total) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  psr::Exec x = make_exec(ctx, sigma, stream);
+  return psr::run_backward(x, res, npoints, chi, dchi, dpoints, dnormals, psr::ws_view(workspace, L),
+                           psr::saved_view(const_cast<void*>(saved), psr::saved_layout(res, npoints)));
+}
+
+int psr_saved_status(const void* saved, hipStream_t stream, int* status) {
+  if (!saved || !status) return PSR_EINVAL;
+  if (hipStreamSynchronize(stream) != hipSuccess) return PSR_EDEVICE;
+  psr::SavedHeader h;
+  if (hipMemcpy(&h, saved, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return PSR_EDEVICE;
+  *status = h.status;
+  return PSR_OK;
+}
+
+int psr_saved_scalars(const void* saved, hipStream_t stream, double* mean, double* cscale, double* scale,
+                      double* chi0) {
+  if (!saved) return PSR_EINVAL;
+  if (hipStreamSynchronize(stream) != hipSuccess) return PSR_EDEVICE;
+  psr::SavedHeader h;
+  if (hipMemcpy(&h, saved, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return PSR_EDEVICE;
+  if (mean) *mean = h.mu;
+  if (cscale) *cscale = h.cscale;
+  if (scale) *scale = h.scale;
+  if (chi0) *chi0 = h.chi0;
+  return PSR_OK;
+}
+
+int psr_run_batched(psr_ctx* ctx, int njobs, const psr_job* jobs, hipStream_t stream) {
+  if (!ctx || njobs < 0 || (njobs > 0 && !jobs)) return PSR_EINVAL;
+  for (int i = 0; i < njobs; ++i) {
+    const psr_job& j = jobs[i];
+    if (!j.points || !j.normals || !j.chi || !j.saved || !j.workspace) return PSR_EINVAL;
+    if (!valid_res(j.res) || !valid_P(j.npoints) || !(j.sigma >= 0.0f) || !std::isfinite(j.sigma))
+      return PSR_EINVAL;
+    if (j.workspace_bytes < psr::ws_layout(j.res, j.npoints).total) return PSR_EINVAL;
+    if (!aligned(j.saved, 256) || !aligned(j.workspace, 256) || !aligned(j.chi, 16)) return PSR_EINVAL;
+    if (j.dchi && !aligned(j.dchi, 16)) return PSR_EINVAL;
+  }
+  for (int i = 0; i < njobs; ++i) {
+    const psr_job& j = jobs[i];
+    int rc = psr_forward(ctx, j.points, j.normals, j.npoints, j.res, j.sigma, j.chi, j.saved, j.workspace,
+                         j.workspace_bytes, stream);
+    if (rc) return rc;
+    if (j.dchi) {
+      rc = psr_backward(ctx, j.npoints, j.res, j.sigma, j.chi, j.saved, j.dchi, j.dpoints, j.dnormals,
+                        j.workspace, j.workspace_bytes, stream);
+      if (rc) return rc;
+    }
+  }
+  return PSR_OK;
+}
+
+int psr_debug_spectral(psr_ctx* ctx, const float* v, int res, float sigma, float* chi_prime, void* workspace,
+                       size_t workspace_bytes, hipStream_t stream) {
+  if (!ctx || !v || !chi_prime || !workspace) return PSR_EINVAL;
+  if (!valid_res(res) || !(sigma >= 0.0f) || !std::isfinite(sigma)) return PSR_EINVAL;
+  if (!aligned(workspace, 256) || !aligned(v, 16)) return PSR_EINVAL;
+  const psr::WsLayout L = psr::ws_layout(res, 1);
+  if (workspace_bytes < L.total) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  psr::Exec x = make_exec(ctx, sigma, stream);
+  return psr::run_debug_spectral(x, res, v, chi_prime, psr::ws_view(workspace, L));
+}
+
+int psr_debug_splat(psr_ctx* ctx, const float* points, const float* normals, int64_t npoints, int res, float* v,
+                    void* saved, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!ctx || !points || !normals || !v || !saved || !workspace) return PSR_EINVAL;
+  if (!valid_res(res) || !valid_P(npoints)) return PSR_EINVAL;
+  if (!aligned(saved, 256) || !aligned(workspace, 256)) return PSR_EINVAL;
+  const psr::WsLayout L = psr::ws_layout(res, npoints);
+  if (workspace_bytes < L.total) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  psr::Exec x = make_exec(ctx, 0.0f, stream);
+  return psr::run_debug_splat(x, res, points, normals, npoints, v, psr::ws_view(workspace, L),
+                              psr::saved_view(saved, psr::saved_layout(res, npoints)));
+}
+
+int psr_ctx_stage_times(psr_ctx* ctx, double* ms, int64_t* counts, int n) {
+  if (!ctx || n < 0) return PSR_EINVAL;
+  if (!ctx->timers) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  ctx->timers->flush();
+  for (int i = 0; i < n && i < psr::NUM_STAGES; ++i) {
+    if (ms) ms[i] = ctx->timers->ms[i];
+    if (counts) counts[i] = ctx->timers->cnt[i];
+  }
+  return PSR_OK;
+}
+
+int psr_ctx_reset_timers(psr_ctx* ctx) {
+  if (!ctx || !ctx->timers) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  ctx->timers->flush();
+  for (int i = 0; i < psr::NUM_STAGES; ++i) {
+    ctx->timers->ms[i] = 0.0;
+    ctx->timers->cnt[i] = 0;
+  }
+  return PSR_OK;
+}
+
+const char* psr_stage_name(int stage) {
+  if (stage < 0 || stage >= psr::NUM_STAGES) return "unknown";
+  return kStageNames[stage];
+}
+
+int psr_num_stages(void) { return psr::NUM_STAGES; }
+
+}  // extern "C"

@@ -1,0 +1,183 @@
+// Shared host/device definitions of the solver library: per-solve state
+// layouts, workspace layout and the launch context.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace psr {
+
+struct cf;
+
+// Sorted point record (32 bytes): fractional cell offsets f, packed floor
+// vertex b (10 bits per axis), normal n, original index.
+struct __align__(16) PointRec {
+  float f0, f1, f2;
+  uint32_t b;
+  float n0, n1, n2;
+  uint32_t idx;
+};
+
+// Head of the `saved` buffer: the forward's status and FP64 scalars.
+struct SavedHeader {
+  int32_t status;   // PSR_OK / PSR_EDEGENERATE / PSR_ENONFINITE
+  int32_t flags;    // bit 0: a non-finite coordinate was seen
+  int32_t res;
+  int32_t reading;  // 0 = B, 1 = A
+  int64_t npoints;
+  float sigma;
+  float m;
+  double mu;        // mean of chi' at the points
+  double cscale;    // c (reading B: chi'(0) - mu; reading A: chi'(0))
+  double scale;     // m / |c|
+  double chi0;      // chi'(0,0,0)
+};
+
+// Backward scalars computed on the device from the FP64 reductions.
+struct BwdScalars {
+  double S_G, S_Gchi, Qd, gmu;
+  float s, q, alpha, pad;
+};
+
+enum Stage {
+  STAGE_BIN = 0,
+  STAGE_P1,
+  STAGE_P2,
+  STAGE_P3,
+  STAGE_P4,
+  STAGE_P5,
+  STAGE_FWD_REDUCE,
+  STAGE_NORMALIZE,
+  STAGE_BWD_REDUCE,
+  STAGE_B1,
+  STAGE_B2,
+  STAGE_B3,
+  STAGE_B4,
+  STAGE_B5,
+  STAGE_BWD_FINAL,
+  NUM_STAGES
+};
+
+constexpr int kRedBlocks = 256;  // fixed block count of the FP64 reductions (deterministic order)
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct WsLayout {
+  size_t bs, blockpart, X, Y, counts, tmp, colrank, part, total;
+};
+
+inline WsLayout ws_layout(int res, int64_t P) {
+  const size_t H = (size_t)res / 2 + 1;
+  const size_t spec = 3 * H * (size_t)res * (size_t)res * 8;
+  WsLayout L;
+  size_t o = 0;
+  L.bs = o;
+  o += align256(sizeof(BwdScalars));
+  L.blockpart = o;
+  o += align256(kRedBlocks * 16);
+  L.X = o;
+  o += align256(spec);
+  L.Y = o;
+  o += align256(spec);
+  L.counts = o;
+  o += align256((size_t)res * res * 4);
+  L.tmp = o;
+  o += align256((size_t)P * sizeof(PointRec));
+  L.colrank = o;
+  o += align256((size_t)P * 8);
+  L.part = o;
+  o += align256((size_t)P * 4 * 32);
+  L.total = o;
+  return L;
+}
+
+struct SavedLayout {
+  size_t hdr, off, sorted, gradf, total;
+};
+
+inline SavedLayout saved_layout(int res, int64_t P) {
+  SavedLayout L;
+  size_t o = 0;
+  L.hdr = o;
+  o += align256(sizeof(SavedHeader));
+  L.off = o;
+  o += align256(((size_t)res * res + 1) * 4);
+  L.sorted = o;
+  o += align256((size_t)P * sizeof(PointRec));
+  L.gradf = o;
+  o += align256((size_t)P * 16);
+  L.total = o;
+  return L;
+}
+
+struct WsView {
+  cf* X;
+  cf* Y;
+  int* counts;
+  PointRec* tmp;
+  int2* colrank;
+  float4* part;
+  double* blockpart;
+  BwdScalars* bs;
+};
+
+struct SavedView {
+  SavedHeader* hdr;
+  int* off;
+  PointRec* sorted;
+  float4* gradf;
+};
+
+inline WsView ws_view(void* base, const WsLayout& L) {
+  char* b = static_cast<char*>(base);
+  WsView w;
+  w.X = reinterpret_cast<cf*>(b + L.X);
+  w.Y = reinterpret_cast<cf*>(b + L.Y);
+  w.counts = reinterpret_cast<int*>(b + L.counts);
+  w.tmp = reinterpret_cast<PointRec*>(b + L.tmp);
+  w.colrank = reinterpret_cast<int2*>(b + L.colrank);
+  w.part = reinterpret_cast<float4*>(b + L.part);
+  w.blockpart = reinterpret_cast<double*>(b + L.blockpart);
+  w.bs = reinterpret_cast<BwdScalars*>(b + L.bs);
+  return w;
+}
+
+inline SavedView saved_view(void* base, const SavedLayout& L) {
+  char* b = static_cast<char*>(base);
+  SavedView s;
+  s.hdr = reinterpret_cast<SavedHeader*>(b + L.hdr);
+  s.off = reinterpret_cast<int*>(b + L.off);
+  s.sorted = reinterpret_cast<PointRec*>(b + L.sorted);
+  s.gradf = reinterpret_cast<float4*>(b + L.gradf);
+  return s;
+}
+
+struct Timers;
+void timer_begin(Timers* t, int stage, hipStream_t s);
+void timer_end(Timers* t, int stage, hipStream_t s);
+
+// Everything a launch sequence needs besides its buffers.
+struct Exec {
+  hipStream_t stream;
+  const cf* tw;  // twiddle tables: table of length L at offset L
+  float sigma;
+  double m;
+  int reading;
+  Timers* timers;  // null when timing is off
+  void begin(int st) {
+    if (timers) timer_begin(timers, st, stream);
+  }
+  void end(int st) {
+    if (timers) timer_end(timers, st, stream);
+  }
+};
+
+int run_forward(Exec& x, int res, const float* pts, const float* nrm, int64_t P, float* chi, const WsView& w,
+                const SavedView& sv);
+int run_backward(Exec& x, int res, int64_t P, const float* chi, const float* dchi, float* dpts, float* dnrm,
+                 const WsView& w, const SavedView& sv);
+int run_debug_spectral(Exec& x, int res, const float* v, float* chi_prime, const WsView& w);
+int run_debug_splat(Exec& x, int res, const float* pts, const float* nrm, int64_t P, float* v, const WsView& w,
+                    const SavedView& sv);
+
+}  // namespace psr

@@ -1,0 +1,64 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and its pure-host calls (sizes, error strings, argument
+validation that fails before any device work) behave as documented."""
+import ctypes
+
+import pytest
+
+from paper_2106_03452_amd import _lib
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.lib()
+
+
+def test_every_header_symbol_is_exported(L):
+    names = _lib.header_symbols()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_strerror_and_version(L):
+    assert L.psr_version() >= 10000
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert L.psr_strerror(code)
+    assert b"unknown" in L.psr_strerror(12345)
+
+
+def test_stage_names(L):
+    n = L.psr_num_stages()
+    names = [L.psr_stage_name(i).decode() for i in range(n)]
+    assert len(set(names)) == n and "P3_fft_j0_spectral_ifft_j0" in names
+    assert L.psr_stage_name(n) == b"unknown"
+
+
+@pytest.mark.parametrize("res", [8, 16, 32, 64, 128, 256, 512])
+def test_workspace_sizes(res):
+    P = 12345
+    ws = _lib.workspace_bytes(res, P)
+    H = res // 2 + 1
+    assert ws >= 2 * 3 * H * res * res * 8 + P * 32
+    assert ws % 256 == 0
+    sv = _lib.saved_bytes(res, P)
+    assert sv >= (res * res + 1) * 4 + P * 48
+
+
+@pytest.mark.parametrize("res,P", [(0, 10), (7, 10), (1024, 10), (4, 10), (96, 10), (64, 0), (64, -5)])
+def test_size_queries_reject_bad_arguments(L, res, P):
+    out = ctypes.c_size_t(0)
+    assert L.psr_workspace_bytes(res, P, 1, ctypes.byref(out)) == _lib.PSR_EINVAL
+    assert L.psr_saved_bytes(res, P, ctypes.byref(out)) == _lib.PSR_EINVAL
+
+
+def test_null_arguments_rejected_without_device_work(L):
+    # every check below fails before any HIP call is made
+    assert L.psr_forward(None, None, None, 10, 64, 2.0, None, None, None, 0, None) == _lib.PSR_EINVAL
+    assert L.psr_backward(None, 10, 64, 2.0, None, None, None, None, None, None, 0, None) == _lib.PSR_EINVAL
+    assert L.psr_ctx_create(None, 0) == _lib.PSR_EINVAL
+    assert L.psr_ctx_destroy(None) == _lib.PSR_EINVAL
+    assert L.psr_ctx_set(None, b"m", 0.5) == _lib.PSR_EINVAL
+    assert L.psr_run_batched(None, 1, None, None) == _lib.PSR_EINVAL
+    assert L.psr_debug_spectral(None, None, 64, 2.0, None, None, 0, None) == _lib.PSR_EINVAL
+    assert L.psr_saved_status(None, None, None) == _lib.PSR_EINVAL

@@ -1,0 +1,239 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances (FP32 grid arithmetic against an FP64 reference):
+  chi, chi', v : max|gpu - ref| / max|ref| <= 1e-5
+  gradients    : ||gpu - ref||_2 / ||ref||_2 <= 1e-4 for dL/dpoints and dL/dnormals
+"""
+import numpy as np
+import pytest
+
+import oracle
+import psr_synth as S
+from gpu_common import announce, host, l2_rel, max_rel, require_gpu, to_dev, torch
+
+pytestmark = pytest.mark.gpu
+
+E_CHI = 1e-5
+E_G = 1e-4
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def psr(dev):
+    import paper_2106_03452_amd as p
+    from paper_2106_03452_amd import function
+    p.context(0)
+    return function
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def assert_forward_close(psr, chi, saved, ref, aux):
+    """Compare a forward with the oracle, accounting for the normalisation's conditioning.
+
+    chi = s (chi' - mean) with s = m/|c|: when |c| is small against max|chi'|
+    (random normals, degenerate clouds) FP32 errors of chi' are amplified by
+    max|chi|/m in chi. The unnormalised chi' (rebuilt from the GPU output and
+    its own FP64 scalars) and c are held to the plain 1e-5 bar; chi to 1e-5
+    times that amplification (>= 1).
+    """
+    sc = psr.scalars(saved)
+    chi_g = host(chi)
+    chip_g = chi_g / sc["scale"] + sc["mean"]
+    span = np.abs(aux["chi_prime"]).max()
+    amp = max(1.0, np.abs(ref).max() / aux["m"])
+    assert max_rel(chip_g, aux["chi_prime"]) < E_CHI
+    assert abs(sc["cscale"] - aux["cscale"]) < E_CHI * span
+    assert max_rel(chi_g, ref) < E_CHI * amp
+
+
+# ------------------------------------------------------------------ stages
+@pytest.mark.parametrize("res,P,kind", [(8, 1, "uniform"), (8, 37, "uniform"), (16, 777, "sphere"),
+                                        (32, 5000, "torus"), (64, 3001, "uniform"), (128, 20000, "sphere")])
+def test_splat_matches_oracle(psr, dev, res, P, kind):
+    announce(f"splat res={res} P={P} kind={kind}")
+    sh = S.tiny_case(res + P, res, P, kind=kind)
+    v = host(psr.debug_splat(to_dev(sh.points, dev), to_dev(sh.normals, dev), res))
+    ref = oracle.splat(sh.points, sh.normals, res)
+    assert max_rel(v, ref) < 2e-6
+
+
+@pytest.mark.parametrize("res,sigma", [(8, 2.0), (16, 0.0), (32, 2.0), (64, 3.5), (128, 2.0)])
+def test_spectral_random_field_matches_oracle(psr, dev, res, sigma):
+    announce(f"spectral random res={res} sigma={sigma}")
+    v = _rng(res).standard_normal((3, res, res, res)).astype(np.float32)
+    out = host(psr.debug_spectral(to_dev(v, dev), sigma))
+    ref, _ = oracle.spectral_solve(v.astype(np.float64), sigma)
+    assert max_rel(out, ref) < E_CHI
+
+
+@pytest.mark.parametrize("res,k,d", [(16, (1, 2, -3), 0), (32, (-5, 7, 2), 1), (64, (3, -11, 20), 2),
+                                     (256, (17, -40, 99), 0), (512, (100, 3, -201), 2)])
+def test_spectral_single_mode_closed_form(psr, dev, res, k, d):
+    announce(f"spectral closed form res={res} k={k} d={d}")
+    sigma = 2.0
+    jj = np.indices((res, res, res), dtype=np.float64) / res
+    th = 2 * np.pi * (k[0] * jj[0] + k[1] * jj[1] + k[2] * jj[2])
+    v = np.zeros((3, res, res, res), dtype=np.float32)
+    v[d] = np.cos(th)
+    K2 = float(np.dot(k, k))
+    expect = np.exp(-2 * sigma ** 2 * K2 / res ** 2) * k[d] * np.sin(th) / (2 * np.pi * K2)
+    out = host(psr.debug_spectral(to_dev(v, dev), sigma))
+    del v, jj
+    assert max_rel(out, expect) < E_CHI
+
+
+def test_spectral_nyquist_and_constant_vanish(psr, dev):
+    res = 32
+    jj = np.indices((res, res, res))
+    v = np.zeros((3, res, res, res), dtype=np.float32)
+    v[0] = (-1.0) ** jj[0]
+    v[1] = 0.25
+    v[2] = -3.0
+    out = host(psr.debug_spectral(to_dev(v, dev), 2.0))
+    assert np.abs(out).max() < 1e-6
+
+
+# ------------------------------------------------------------------ forward
+CASES = [(8, 1, "uniform", 2.0), (8, 9, "uniform", 0.0), (16, 300, "sphere", 2.0), (16, 513, "uniform", 1.0),
+         (32, 2049, "torus", 2.0), (64, 4000, "sphere", 3.0), (64, 10007, "uniform", 2.0)]
+
+
+@pytest.mark.parametrize("res,P,kind,sigma", CASES)
+def test_forward_matches_oracle(psr, dev, res, P, kind, sigma):
+    announce(f"forward res={res} P={P} kind={kind} sigma={sigma}")
+    sh = S.tiny_case(7 * res + P, res, P, sigma, kind=kind)
+    chi, saved = psr.forward(to_dev(sh.points, dev), to_dev(sh.normals, dev), res, sigma)
+    assert psr.status(saved) == 0
+    ref, aux = oracle.forward(sh.points, sh.normals, res, sigma)
+    assert max_rel(host(chi), ref) < E_CHI
+    sc = psr.scalars(saved)
+    scale_ref = abs(aux["cscale"])
+    assert abs(sc["mean"] - aux["mu"]) <= 1e-5 * scale_ref
+    assert abs(sc["cscale"] - aux["cscale"]) <= 1e-5 * scale_ref
+
+
+def test_forward_c1_sphere(psr, dev):
+    sh = S.config_c1()
+    announce("forward C1 32^3 sphere 3000")
+    chi, saved = psr.forward(to_dev(sh.points, dev), to_dev(sh.normals, dev), 32, 2.0)
+    ref, _ = oracle.forward(sh.points, sh.normals, 32, 2.0)
+    e = max_rel(host(chi), ref)
+    print(f"C1 e_chi = {e:.3e}")
+    assert e < E_CHI
+
+
+# ------------------------------------------------------------------ backward
+@pytest.mark.parametrize("res,P,kind,reading", [(8, 5, "uniform", 0), (16, 300, "torus", 0), (32, 2000, "sphere", 0),
+                                                (32, 1500, "uniform", 1), (64, 6000, "torus", 0)])
+def test_backward_matches_oracle(psr, dev, res, P, kind, reading):
+    announce(f"backward res={res} P={P} kind={kind} reading={reading}")
+    import paper_2106_03452_amd as p
+    ctx = p.context(0)
+    ctx.set("reading", reading)
+    try:
+        sh = S.tiny_case(11 * res + P, res, P, 2.0, kind=kind)
+        G = _rng(res + P).standard_normal((res, res, res))
+        pts, nrm = to_dev(sh.points, dev), to_dev(sh.normals, dev)
+        chi, saved = psr.forward(pts, nrm, res, 2.0)
+        dp, dn = psr.backward(chi, saved, to_dev(G, dev), P, res, 2.0)
+        ref, aux = oracle.forward(sh.points, sh.normals, res, 2.0, reading="B" if reading == 0 else "A")
+        dc_ref, dn_ref = oracle.backward(aux, G.astype(np.float32).astype(np.float64))
+        assert max_rel(host(chi), ref) < E_CHI
+        assert l2_rel(host(dn), dn_ref) < E_G
+        assert l2_rel(host(dp), dc_ref) < E_G
+    finally:
+        ctx.set("reading", 0)
+
+
+def test_autograd_function_matches_explicit_backward(psr, dev):
+    announce("autograd 32^3")
+    sh = S.tiny_case(5, 32, 1000, kind="torus")
+    pts = to_dev(sh.points, dev).requires_grad_(True)
+    nrm = to_dev(sh.normals, dev).requires_grad_(True)
+    chi = psr.solve(pts, nrm, 32, 2.0)
+    G = torch.randn(32, 32, 32, device=dev, generator=torch.Generator(device=dev).manual_seed(0))
+    (chi * G).sum().backward()
+    ref, aux = oracle.forward(sh.points, sh.normals, 32, 2.0)
+    dc_ref, dn_ref = oracle.backward(aux, host(G))
+    assert l2_rel(host(pts.grad), dc_ref) < E_G
+    assert l2_rel(host(nrm.grad), dn_ref) < E_G
+
+
+# ------------------------------------------------------------------ edge cases
+def test_single_point_and_one_column(psr, dev):
+    announce("edge: P=1 and a single column")
+    for res, pts in [(16, np.array([[0.3, 0.6, 0.1]])),
+                     (32, np.stack([np.full(400, 0.5), np.full(400, 0.25), np.linspace(0, 1, 400, endpoint=False)], 1))]:
+        nrm = _rng(res).standard_normal(pts.shape)
+        chi, saved = psr.forward(to_dev(pts, dev), to_dev(nrm, dev), res, 2.0)
+        ref, aux = oracle.forward(pts.astype(np.float32), nrm.astype(np.float32), res, 2.0)
+        assert_forward_close(psr, chi, saved, ref, aux)
+
+
+def test_wrapped_and_boundary_coordinates(psr, dev):
+    announce("edge: coordinates outside [0,1) and on vertices")
+    res = 32
+    rng = _rng(3)
+    pts = rng.uniform(-2.0, 3.0, (3000, 3)).astype(np.float32)
+    pts[:50] = (rng.integers(0, res, (50, 3)) / res).astype(np.float32)  # exactly on vertices
+    pts[50:60] = 0.0
+    pts[60:70] = 1.0
+    nrm = rng.standard_normal((3000, 3)).astype(np.float32)
+    chi, saved = psr.forward(to_dev(pts, dev), to_dev(nrm, dev), res, 2.0)
+    ref, aux = oracle.forward(pts, nrm, res, 2.0)
+    assert_forward_close(psr, chi, saved, ref, aux)
+
+
+def test_degenerate_and_nonfinite_status(psr, dev):
+    announce("edge: zero normals and NaN coordinates")
+    pts = _rng(0).uniform(0, 1, (100, 3)).astype(np.float32)
+    chi, saved = psr.forward(to_dev(pts, dev), torch.zeros(100, 3, device=dev), 16, 2.0)
+    assert psr.status(saved) == -3 and torch.isnan(chi).all()
+    bad = pts.copy()
+    bad[7, 1] = np.nan
+    chi, saved = psr.forward(to_dev(bad, dev), to_dev(np.ones((100, 3)), dev), 16, 2.0)
+    assert psr.status(saved) == -6 and torch.isnan(chi).all()
+
+
+def test_bad_arguments_raise(psr, dev):
+    import paper_2106_03452_amd as p
+    pts = torch.rand(10, 3, device=dev)
+    for res in (4, 48, 1024):
+        with pytest.raises(Exception):
+            psr.forward(pts, pts, res, 2.0)
+    with pytest.raises(p.PSRError):
+        psr.forward(pts, pts, 16, -1.0)
+
+
+def test_options_m_and_sign_flip(psr, dev):
+    announce("options m and exact sign flip")
+    import paper_2106_03452_amd as p
+    ctx = p.context(0)
+    sh = S.tiny_case(8, 64, 3000, kind="torus")
+    pts, nrm = to_dev(sh.points, dev), to_dev(sh.normals, dev)
+    chi, _ = psr.forward(pts, nrm, 64, 2.0)
+    chin, _ = psr.forward(pts, -nrm, 64, 2.0)
+    # every step is odd in the normals; only the splat's atomic summation order differs
+    assert max_rel(host(chin), -host(chi)) < 1e-6
+    ctx.set("m", 0.7)
+    try:
+        chi7, _ = psr.forward(pts, nrm, 64, 2.0)
+    finally:
+        ctx.set("m", 0.5)
+    assert abs(abs(float(chi7[0, 0, 0])) - 0.7) < 1e-6
+    assert max_rel(host(chi7), host(chi) * 1.4) < 1e-6
+
+
+def test_repeat_is_stable(psr, dev):
+    sh = S.tiny_case(9, 64, 8000, kind="sphere")
+    pts, nrm = to_dev(sh.points, dev), to_dev(sh.normals, dev)
+    a, _ = psr.forward(pts, nrm, 64, 2.0)
+    b, _ = psr.forward(pts, nrm, 64, 2.0)
+    assert max_rel(host(a), host(b)) < 1e-6
