@@ -46,20 +46,20 @@ def stage_bytes(r: int, P: int) -> dict:
     N4 = 4 * r ** 3
     return {
         "bin": 24 * P + 32 * P * 2 + 8 * P,
-        "P1_splat_r2c": 32 * P + 3 * S,
-        "P2_fft_j1": 6 * S,
-        "P3_fft_j0_spectral_ifft_j0": 3 * S + S,
+        "P1_splat_r2c": 32 * P + 3 * S,             # sorted points in, 3 half-spectra out
+        "P2_fft_j1": 3 * S + 2 * S,                 # 3 channels in, v~_0 and merged W out
+        "P3_fft_j0_spectral_ifft_j0": 2 * S + S,    # 2 in, chi~ (after the k0 inverse) out
         "P4_ifft_j1": 2 * S,
-        "P5_c2r_gather": S + N4 + 32 * P + 64 * P,
+        "P5_c2r_gather": S + N4 + 32 * P + 64 * P,  # chi' written, gather partials
         "fwd_reduce": 64 * P + 16 * P,
         "normalize": 2 * N4,
         "bwd_reduce": 2 * N4,
         "B1_cotangent_r2c": N4 + 32 * P + S,
         "B2_fft_j1": 2 * S,
-        "B3_fft_j0_conjop_ifft_j0": S + 3 * S,
-        "B4_ifft_j1": 6 * S,
-        "B5_c2r_gather": 3 * S + 32 * P + 128 * P,
-        "bwd_finalize": 128 * P + 16 * P + 32 * P + 24 * P,
+        "B3_fft_j0_conjop_ifft_j0": S + 2 * S,      # 1 in, kappa_0 channel and unscaled U out
+        "B4_ifft_j1": 2 * S + 3 * S,                # 2 in, 3 out
+        "B5_c2r_gather": 3 * S + 32 * P + 192 * P,  # upper bound: tiles without points are skipped
+        "bwd_finalize": 192 * P + 16 * P + 32 * P + 24 * P,
     }
 
 
@@ -188,6 +188,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 128^3 and forward-only lines")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 1 GiB five times (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X (its multi-GPU slab "
@@ -195,11 +197,25 @@ def main():
         sys.exit(2)
 
     import torch
+    dev = torch.device("cuda", 0)
+    if args.calibrate_copy:
+        n = 1 << 28  # 2^28 float32 = 1 GiB
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "ms": round(dt * 1e3, 4),
+                          "GBs_read_plus_write": round(8 * n / dt / 1e9, 1)}), flush=True)
+        return
+
     import psr_synth as S
     from paper_2106_03452_amd import _lib
     from paper_2106_03452_amd import function as F
 
-    dev = torch.device("cuda", 0)
     ctx = _lib.context(0)
     shape = S.config_c3()
     b = prepare(shape, dev, torch, F)

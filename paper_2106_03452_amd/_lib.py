@@ -14,7 +14,8 @@ import re
 import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpsr.so")
+# PSR_LIBRARY overrides the library path (A/B comparisons of build variants)
+LIB_PATH = os.environ.get("PSR_LIBRARY") or os.path.join(HERE, "libpsr.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "psr.h")
 
 PSR_OK = 0

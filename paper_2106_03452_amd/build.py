@@ -22,28 +22,28 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build libpsr.so)")
 
 
-def compile_command(out: str) -> list[str]:
+def compile_command(out: str, defines: tuple[str, ...] = ()) -> list[str]:
     return [
         hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
         # packed-FP32 instructions stay off in every HIP object of this library
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wno-unused-command-line-argument",
         "-I", INCLUDE, "-I", CSRC, "-o", out,
-    ] + [os.path.join(CSRC, s) for s in SOURCES]
+    ] + [f"-D{d}" for d in defines] + [os.path.join(CSRC, s) for s in SOURCES]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, defines: tuple[str, ...] = ()) -> str:
     """Compile the library (always recompiles) and return its path."""
-    tmp = LIB + ".tmp"
-    cmd = compile_command(tmp)
+    tmp = out + ".tmp"
+    cmd = compile_command(tmp, defines)
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, capture_output=True, text=True)
     if proc.returncode != 0:
         sys.stderr.write(proc.stdout + proc.stderr)
         raise RuntimeError(f"hipcc failed with exit code {proc.returncode}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

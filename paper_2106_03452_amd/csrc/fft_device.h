@@ -10,9 +10,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "psr_geometry.h"
+
 namespace psr {
 
-constexpr int kBlock = 256;  // threads per workgroup of every grid pass
 
 struct cf {
   float x, y;
@@ -130,96 +131,83 @@ __device__ __forceinline__ void dft(cf* a) {
 __host__ __device__ constexpr int lstride(int L) { return L + L / 16 + 1; }
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 
-// One Stockham autosort radix-R stage on a line of length L held in LDS.
-// Stage input is the output of the previous stage (NS = product of earlier
-// radices). Butterfly j reads elements j + m L/R, applies the twiddles
-// exp(DIR 2 pi i m k/(NS R)) with k = j mod NS, does a radix-R DFT and writes
-// to (j - k) R + k + q NS. Each thread owns E elements (E/R butterflies);
+// Canonical register layout of a line (plan_TPL(L) threads, plan_E(L)
+// elements each): reg[v] holds element lt + TPL * v of the line (lt = the
+// thread's index within its line). Every radix plan below reads its first
+// stage from, and writes its last stage to, exactly that set.
+
+// One Stockham autosort radix-R stage of a length-L line. Butterfly j
+// (j = lt + TPL u) reads elements j + m L/R, multiplies them by the twiddles
+// exp(DIR 2 pi i m k / (NS R)) with k = j mod NS (NS = product of the earlier
+// radices), does a radix-R DFT and writes element (j - k) R + k + q NS.
+// IN_REG: inputs come from the canonical registers (first stage only),
+// otherwise from the LDS line. OUT_REG: outputs go to the canonical
+// registers (last stage only), otherwise to the LDS line. A stage that reads
+// LDS ends its reads with a barrier; one that writes LDS ends with a barrier.
+// A first stage that writes LDS assumes the line is no longer being read.
 // `tw` is the table exp(-2 pi i e / L), e in [0, L).
-template <int L, int R, int NS, int DIR, int E>
-__device__ __forceinline__ void stockham_stage(cf* line, int lt, bool active, const cf* __restrict__ tw) {
-  constexpr int TPL = L / E;
+template <int L, int R, int NS, int DIR, bool IN_REG, bool OUT_REG>
+__device__ __forceinline__ void stage(cf* reg, cf* line, int lt, const cf* __restrict__ tw) {
+  constexpr int E = plan_E(L), TPL = plan_TPL(L);
   constexpr int NB = E / R;
   constexpr int STRIDE = L / R;
   cf a[NB][R];
-  if (active) {
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int j = lt + TPL * u;
+  for (int u = 0; u < NB; ++u) {
+    const int j = lt + TPL * u;
 #pragma unroll
-      for (int m = 0; m < R; ++m) a[u][m] = line[pidx(j + m * STRIDE)];
-    }
+    for (int m = 0; m < R; ++m) a[u][m] = IN_REG ? reg[u + m * NB] : line[pidx(j + m * STRIDE)];
   }
-  __syncthreads();
-  if (active) {
+  if constexpr (!IN_REG) __syncthreads();
 #pragma unroll
-    for (int u = 0; u < NB; ++u) {
-      const int j = lt + TPL * u;
-      const int k = j & (NS - 1);
-      if constexpr (NS > 1) {
+  for (int u = 0; u < NB; ++u) {
+    const int j = lt + TPL * u;
+    const int k = j & (NS - 1);
+    if constexpr (NS > 1) {
 #pragma unroll
-        for (int m = 1; m < R; ++m) {
-          cf w = tw[m * k * (L / (NS * R))];
-          if constexpr (DIR > 0) w.y = -w.y;
-          a[u][m] = cmul(a[u][m], w);
-        }
+      for (int m = 1; m < R; ++m) {
+        cf w = tw[m * k * (L / (NS * R))];
+        if constexpr (DIR > 0) w.y = -w.y;
+        a[u][m] = cmul(a[u][m], w);
       }
-      dft<R, DIR>(a[u]);
-      const int base = (j - k) * R + k;
+    }
+    dft<R, DIR>(a[u]);
+    const int base = (j - k) * R + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) line[pidx(base + q * NS)] = a[u][q];
+    for (int q = 0; q < R; ++q) {
+      if constexpr (OUT_REG) reg[u + q * NB] = a[u][q];
+      else line[pidx(base + q * NS)] = a[u][q];
     }
   }
-  __syncthreads();
+  if constexpr (!OUT_REG) __syncthreads();
 }
 
-// Full length-L transform of one line, radix plan chosen per L so that each
-// thread owns 16 elements (L/16 threads per line; one thread for L < 16).
-template <int L>
-struct LinePlan {
-  static constexpr int E = L < 16 ? L : 16;
-  static constexpr int TPL = L / E;
-};
-
-template <int L, int DIR>
-__device__ __forceinline__ void fft_line(cf* line, int lt, bool active, const cf* __restrict__ tw) {
-  constexpr int E = LinePlan<L>::E;
+// Whole length-L transform. IN_REG / OUT_REG select where the first stage
+// reads and the last stage writes (canonical registers or the LDS line).
+template <int L, int DIR, bool IN_REG, bool OUT_REG>
+__device__ __forceinline__ void fft(cf* reg, cf* line, int lt, const cf* __restrict__ tw) {
   if constexpr (L == 4) {
-    stockham_stage<4, 4, 1, DIR, E>(line, lt, active, tw);
+    stage<4, 4, 1, DIR, IN_REG, OUT_REG>(reg, line, lt, tw);
   } else if constexpr (L == 8) {
-    stockham_stage<8, 8, 1, DIR, E>(line, lt, active, tw);
+    stage<8, 8, 1, DIR, IN_REG, OUT_REG>(reg, line, lt, tw);
   } else if constexpr (L == 16) {
-    stockham_stage<16, 16, 1, DIR, E>(line, lt, active, tw);
+    stage<16, 16, 1, DIR, IN_REG, OUT_REG>(reg, line, lt, tw);
   } else if constexpr (L == 32) {
-    stockham_stage<32, 8, 1, DIR, E>(line, lt, active, tw);
-    stockham_stage<32, 4, 8, DIR, E>(line, lt, active, tw);
+    stage<32, 8, 1, DIR, IN_REG, false>(reg, line, lt, tw);
+    stage<32, 4, 8, DIR, false, OUT_REG>(reg, line, lt, tw);
   } else if constexpr (L == 64) {
-    stockham_stage<64, 8, 1, DIR, E>(line, lt, active, tw);
-    stockham_stage<64, 8, 8, DIR, E>(line, lt, active, tw);
+    stage<64, 8, 1, DIR, IN_REG, false>(reg, line, lt, tw);
+    stage<64, 8, 8, DIR, false, OUT_REG>(reg, line, lt, tw);
   } else if constexpr (L == 128) {
-    stockham_stage<128, 16, 1, DIR, E>(line, lt, active, tw);
-    stockham_stage<128, 8, 16, DIR, E>(line, lt, active, tw);
+    stage<128, 16, 1, DIR, IN_REG, false>(reg, line, lt, tw);
+    stage<128, 8, 16, DIR, false, OUT_REG>(reg, line, lt, tw);
   } else if constexpr (L == 256) {
-    stockham_stage<256, 16, 1, DIR, E>(line, lt, active, tw);
-    stockham_stage<256, 16, 16, DIR, E>(line, lt, active, tw);
+    stage<256, 16, 1, DIR, IN_REG, false>(reg, line, lt, tw);
+    stage<256, 16, 16, DIR, false, OUT_REG>(reg, line, lt, tw);
   } else if constexpr (L == 512) {
-    stockham_stage<512, 8, 1, DIR, E>(line, lt, active, tw);
-    stockham_stage<512, 8, 8, DIR, E>(line, lt, active, tw);
-    stockham_stage<512, 8, 64, DIR, E>(line, lt, active, tw);
-  }
-}
-
-// Transform `nlines` lines (stride `ls` slots) in LDS with the whole
-// workgroup; every thread takes part in every barrier.
-template <int L, int DIR>
-__device__ __forceinline__ void fft_lines(cf* buf, int nlines, int ls, const cf* __restrict__ tw) {
-  constexpr int TPL = LinePlan<L>::TPL;
-  constexpr int LPR = kBlock / TPL;
-  const int t = threadIdx.x;
-  for (int base = 0; base < nlines; base += LPR) {
-    const int line = base + t / TPL;
-    const bool active = line < nlines;
-    fft_line<L, DIR>(buf + (active ? line : 0) * ls, t % TPL, active, tw);
+    stage<512, 8, 1, DIR, IN_REG, false>(reg, line, lt, tw);
+    stage<512, 8, 8, DIR, false, false>(reg, line, lt, tw);
+    stage<512, 8, 64, DIR, false, OUT_REG>(reg, line, lt, tw);
   }
 }
 

@@ -1,0 +1,34 @@
+// Work decomposition shared by the host launch code and the device kernels.
+#pragma once
+
+// Threads per workgroup of the column passes and of the row passes.
+#ifndef PSR_COL_THREADS
+#define PSR_COL_THREADS 256
+#endif
+#ifndef PSR_ROW_THREADS
+#define PSR_ROW_THREADS 256
+#endif
+
+namespace psr {
+
+// Work split of a length-L line FFT: plan_TPL(L) threads per line, each
+// holding plan_E(L) elements in registers.
+__host__ __device__ constexpr int plan_E(int L) { return L < 16 ? L : 16; }
+__host__ __device__ constexpr int plan_TPL(int L) { return L / plan_E(L); }
+__host__ __device__ constexpr int imin(int a, int b) { return a < b ? a : b; }
+
+// Column passes (FFT along j1 / j0, length res): tile_cols(res) lines per
+// workgroup of cols_block(res) threads.
+__host__ __device__ constexpr int tile_cols(int res) { return imin(res, PSR_COL_THREADS / plan_TPL(res)); }
+__host__ __device__ constexpr int cols_block(int res) { return tile_cols(res) * plan_TPL(res); }
+
+// Row passes (splat + r2c and c2r + gather along j2; half-length complex
+// lines of res/2): tile_rows(res) consecutive j1 lines of one j0 per
+// workgroup of rows_block(res) threads. Points are binned by these tiles:
+// bin = b0 * row_tiles(res) + b1 / tile_rows(res).
+__host__ __device__ constexpr int tile_rows(int res) { return imin(res, PSR_ROW_THREADS / plan_TPL(res / 2)); }
+__host__ __device__ constexpr int rows_block(int res) { return tile_rows(res) * plan_TPL(res / 2); }
+__host__ __device__ constexpr int row_tiles(int res) { return res / tile_rows(res); }
+__host__ __device__ constexpr int num_bins(int res) { return res * row_tiles(res); }
+
+}  // namespace psr

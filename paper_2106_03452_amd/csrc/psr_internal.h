@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "psr_geometry.h"
+
 namespace psr {
 
 struct cf;
@@ -58,7 +60,7 @@ enum Stage {
   NUM_STAGES
 };
 
-constexpr int kRedBlocks = 256;  // fixed block count of the FP64 reductions (deterministic order)
+constexpr int kRedBlocks = 1024;  // fixed block count of the FP64 reductions (deterministic order)
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -80,13 +82,13 @@ inline WsLayout ws_layout(int res, int64_t P) {
   L.Y = o;
   o += align256(spec);
   L.counts = o;
-  o += align256((size_t)res * res * 4);
+  o += align256((size_t)num_bins(res) * 4);
   L.tmp = o;
   o += align256((size_t)P * sizeof(PointRec));
   L.colrank = o;
   o += align256((size_t)P * 8);
   L.part = o;
-  o += align256((size_t)P * 4 * 32);
+  o += align256((size_t)P * 4 * 3 * 16);  // per point, corner line and channel: 4 floats
   L.total = o;
   return L;
 }
@@ -101,7 +103,7 @@ inline SavedLayout saved_layout(int res, int64_t P) {
   L.hdr = o;
   o += align256(sizeof(SavedHeader));
   L.off = o;
-  o += align256(((size_t)res * res + 1) * 4);
+  o += align256(((size_t)num_bins(res) + 1) * 4);
   L.sorted = o;
   o += align256((size_t)P * sizeof(PointRec));
   L.gradf = o;

@@ -1,11 +1,12 @@
 // gfx950 kernels of the differentiable Poisson solver (Peng et al., NeurIPS 2021).
 //
 // Pipeline of one forward solve (main Sec. 3.1, Eqs. 2-4; supplement Sec. A):
-//   bin      points -> column (b0, b1) buckets (count, scan, scatter)
+//   bin      points -> row-tile buckets (count, scan, scatter)
 //   P1       splat normals into LDS rows + real-to-complex FFT along j2
 //            (supplement A.1 rasterisation fused with the first FFT axis)
-//   P2       FFT along j1 (3 channels)
-//   P3       FFT along j0, spectral operator of main Eq. 3 summed over the 3
+//   P2       FFT along j1 (3 channels in; out v~_0 and the merged channel
+//            W = kappa_1 v~_1 + kappa_2 v~_2)
+//   P3       FFT along j0, spectral operator of main Eq. 3 summed over the
 //            channels, inverse FFT along j0 (one channel out)
 //   P4       inverse FFT along j1
 //   P5       complex-to-real inverse FFT along j2, write chi', and the
@@ -15,12 +16,15 @@
 // cotangent H, conjugate operator, 3 inverse channels, gather of dL/dv).
 //
 // Layouts (complex64 unless noted; H = r/2 + 1 half-spectrum planes):
-//   A[c][k2][j0][j1]   P1 out, P2 in
-//   B[c][k1][k2][j0]   P2 out, P3 in
-//   C[c][j0][k2][k1]   P3 out, P4 in
-//   D[c][k2][j0][j1]   P4 out, P5 in
-// Each pass reads whole contiguous lines or 16-line segments and writes the
-// other, so every global access is at least a 128-byte run.
+//   A[c][k2][j0][j1]   P1 out, P2 in   (3 channels fwd, 1 bwd)
+//   B[c][k1][k2][j0]   P2 out, P3 in   (2 fwd, 1 bwd)
+//   C[c][j0][k2][k1]   P3 out, P4 in   (1 fwd, 2 bwd)
+//   D[c][k2][j0][j1]   P4 out, P5 in   (1 fwd, 3 bwd)
+// Each pass reads whole contiguous lines or multi-line segments and writes
+// the other, so every global access is at least a 128-byte run. FFT data
+// stays in registers between the global load, the first and last radix
+// stages and the store; LDS carries only the exchange between stages and the
+// transposes of segment stores.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -29,8 +33,6 @@
 #include "psr_internal.h"
 
 namespace psr {
-
-__host__ __device__ constexpr int tile_lines(int res) { return res >= 512 ? 8 : (res >= 16 ? 16 : res); }
 
 __device__ __forceinline__ float kappa_of(int k, int res) { return (float)(k < res / 2 ? k : k - res); }
 // odd (first-derivative) factor: zero at the Nyquist index
@@ -42,36 +44,45 @@ __device__ __forceinline__ void load_rec(const PointRec* __restrict__ s, int64_t
   b = p[1];
 }
 
-// Point ranges (in sorted order) whose 2x2 corner lines can touch the tile of
-// lines (j0, j1 in [a0, a0+T)): floor columns b0 in {j0-1, j0},
-// b1 in [a0-1, a0+T-1] (mod res). Up to 4 disjoint ranges.
-template <int RES, int T>
-__device__ __forceinline__ int tile_ranges(const int* __restrict__ off, int j0, int a0, int* lo, int* hi) {
+// Point ranges (in sorted order) whose 2x2 corner lines can touch the row
+// tile (j0, j1 in [tb*TR, tb*TR + TR)): bins of floor rows b0 in {j0-1, j0}
+// and of row tiles tb-1 and tb (the last column of tile tb-1 reaches line
+// tb*TR through its +1 corner). Up to 4 disjoint ranges.
+template <int RES>
+__device__ __forceinline__ int tile_ranges(const int* __restrict__ off, int j0, int tb, int* lo, int* hi) {
+  constexpr int NT = row_tiles(RES);
   int nr = 0;
 #pragma unroll
   for (int o = 0; o < 2; ++o) {
-    const int b0 = (j0 - 1 + o) & (RES - 1);
-    const int rb = b0 * RES;
-    if constexpr (T == RES) {
+    const int rb = ((j0 - 1 + o) & (RES - 1)) * NT;
+    if constexpr (NT == 1) {
       lo[nr] = off[rb];
-      hi[nr] = off[rb + RES];
+      hi[nr] = off[rb + 1];
       ++nr;
     } else {
-      if (a0 > 0) {
-        lo[nr] = off[rb + a0 - 1];
-        hi[nr] = off[rb + a0 + T];
+      if (tb > 0) {
+        lo[nr] = off[rb + tb - 1];
+        hi[nr] = off[rb + tb + 1];
         ++nr;
       } else {
-        lo[nr] = off[rb + RES - 1];
-        hi[nr] = off[rb + RES];
+        lo[nr] = off[rb + NT - 1];
+        hi[nr] = off[rb + NT];
         ++nr;
         lo[nr] = off[rb];
-        hi[nr] = off[rb + T];
+        hi[nr] = off[rb + 1];
         ++nr;
       }
     }
   }
   return nr;
+}
+
+// Copy the twiddle table of length L (exp(-2 pi i e / L), e in [0, n)) into
+// LDS; the first barrier of the caller makes it visible. Loaded at kernel
+// start so the copy overlaps the data loads instead of stalling a stage.
+template <int BLOCK>
+__device__ __forceinline__ void stage_table(cf* dst, const cf* __restrict__ src, int n) {
+  for (int e = threadIdx.x; e < n; e += BLOCK) dst[e] = src[e];
 }
 
 __device__ __forceinline__ int64_t range_pick(const int* lo, const int* hi, int nr, int q) {
@@ -84,7 +95,7 @@ __device__ __forceinline__ int64_t range_pick(const int* lo, const int* hi, int 
 }
 
 // ---------------------------------------------------------------------------
-// binning (counting sort of the points by floor column (b0, b1))
+// binning: counting sort of the points by row tile (b0, b1 / tile_rows)
 // ---------------------------------------------------------------------------
 __global__ void k_init(int* __restrict__ counts, int n, SavedHeader* __restrict__ hdr, int res,
                        int64_t npoints, float sigma, float m, int reading) {
@@ -100,74 +111,115 @@ __global__ void k_init(int* __restrict__ counts, int n, SavedHeader* __restrict_
   }
 }
 
+// Each workgroup takes kBinChunk points, counts them per bin in LDS (local
+// rank = the LDS atomic's return value), then reserves its slots in every
+// bin it touched with one global atomic per bin: few global atomics per bin
+// even when a surface crowds the points into a few bins.
+constexpr int kBinChunk = 1024;
+
 template <int RES>
-__global__ void k_bin(const float* __restrict__ pts, const float* __restrict__ nrm, int64_t npoints,
-                      int* __restrict__ counts, PointRec* __restrict__ tmp, int2* __restrict__ colrank,
-                      SavedHeader* __restrict__ hdr) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npoints) return;
-  float f[3], n[3];
-  int b[3];
-  bool bad = false;
+__global__ __launch_bounds__(256) void k_bin(const float* __restrict__ pts, const float* __restrict__ nrm,
+                                             int64_t npoints, int* __restrict__ counts,
+                                             PointRec* __restrict__ tmp, int2* __restrict__ colrank,
+                                             SavedHeader* __restrict__ hdr) {
+  constexpr int NB = num_bins(RES);
+  constexpr int PPT = kBinChunk / 256;
+  __shared__ int hist[NB];
+  const int t = threadIdx.x;
+  for (int e = t; e < NB; e += 256) hist[e] = 0;
+  __syncthreads();
+  int mybin[PPT], myrank[PPT];
+  bool anybad = false;
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    float x = pts[3 * i + a];
-    n[a] = nrm[3 * i + a];
-    if (!isfinite(x)) {
-      bad = true;
-      x = 0.0f;
+  for (int u = 0; u < PPT; ++u) {
+    const int64_t i = (int64_t)blockIdx.x * kBinChunk + u * 256 + t;
+    mybin[u] = -1;
+    if (i >= npoints) continue;
+    float f[3], n[3];
+    int b[3];
+    bool bad = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      float x = pts[3 * i + a];
+      n[a] = nrm[3 * i + a];
+      if (!isfinite(x)) {
+        bad = true;
+        x = 0.0f;
+      }
+      float uu = x - floorf(x);  // wrap into [0,1): periodic domain
+      if (uu >= 1.0f) uu = 0.0f;
+      const float tt = uu * (float)RES;  // exact: RES is a power of two
+      int bi = (int)floorf(tt);
+      bi = bi < 0 ? 0 : (bi > RES - 1 ? RES - 1 : bi);
+      b[a] = bi;
+      f[a] = tt - (float)bi;
     }
-    float u = x - floorf(x);  // wrap into [0,1): periodic domain
-    if (u >= 1.0f) u = 0.0f;
-    const float t = u * (float)RES;  // exact: RES is a power of two
-    int bi = (int)floorf(t);
-    bi = bi < 0 ? 0 : (bi > RES - 1 ? RES - 1 : bi);
-    b[a] = bi;
-    f[a] = t - (float)bi;
+    if (bad) {
+      f[0] = f[1] = f[2] = 0.0f;
+      n[0] = n[1] = n[2] = 0.0f;
+      anybad = true;
+    }
+    const int bin = b[0] * row_tiles(RES) + b[1] / tile_rows(RES);
+    mybin[u] = bin;
+    myrank[u] = atomicAdd(&hist[bin], 1);
+    PointRec r;
+    r.f0 = f[0];
+    r.f1 = f[1];
+    r.f2 = f[2];
+    r.b = (uint32_t)b[0] | ((uint32_t)b[1] << 10) | ((uint32_t)b[2] << 20);
+    r.n0 = n[0];
+    r.n1 = n[1];
+    r.n2 = n[2];
+    r.idx = (uint32_t)i;
+    tmp[i] = r;
   }
-  if (bad) {
-    f[0] = f[1] = f[2] = 0.0f;
-    n[0] = n[1] = n[2] = 0.0f;
-    atomicOr(&hdr->flags, 1);
+  if (anybad) atomicOr(&hdr->flags, 1);
+  __syncthreads();
+  for (int e = t; e < NB; e += 256) {
+    const int cnt = hist[e];
+    hist[e] = cnt ? atomicAdd(&counts[e], cnt) : 0;
   }
-  const int col = b[0] * RES + b[1];
-  const int rank = atomicAdd(&counts[col], 1);
-  PointRec r;
-  r.f0 = f[0];
-  r.f1 = f[1];
-  r.f2 = f[2];
-  r.b = (uint32_t)b[0] | ((uint32_t)b[1] << 10) | ((uint32_t)b[2] << 20);
-  r.n0 = n[0];
-  r.n1 = n[1];
-  r.n2 = n[2];
-  r.idx = (uint32_t)i;
-  tmp[i] = r;
-  colrank[i] = make_int2(col, rank);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int64_t i = (int64_t)blockIdx.x * kBinChunk + u * 256 + t;
+    if (mybin[u] >= 0) colrank[i] = make_int2(mybin[u], hist[mybin[u]] + myrank[u]);
+  }
 }
 
-// Exclusive scan of n counts into off[0..n] with one workgroup of 1024.
+// Exclusive scan of n counts into off[0..n]: one workgroup of 1024 threads,
+// coalesced rounds of 1024 elements, wavefront shuffles + a carry.
 __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ counts, int* __restrict__ off, int n) {
-  __shared__ int sums[1024];
-  const int t = threadIdx.x;
-  const int chunk = (n + 1023) / 1024;
-  const int lo = t * chunk;
-  const int hi = min(lo + chunk, n);
-  int s = 0;
-  for (int i = lo; i < hi; ++i) s += counts[i];
-  sums[t] = s;
-  __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    const int v = t >= d ? sums[t - d] : 0;
+  __shared__ int wsum[16];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  int carry = 0;
+  for (int base = 0; base < n; base += 1024) {
+    const int i = base + t;
+    const int c = i < n ? counts[i] : 0;
+    int v = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(v, d, 64);
+      if (lane >= d) v += y;
+    }
+    if (lane == 63) wsum[wid] = v;
     __syncthreads();
-    sums[t] += v;
+    if (wid == 0) {
+      int w = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+      for (int d = 1; d < 16; d <<= 1) {
+        const int y = __shfl_up(w, d, 64);
+        if (lane >= d) w += y;
+      }
+      if (lane < 16) wsum[lane] = w;
+    }
+    __syncthreads();
+    const int before = (wid ? wsum[wid - 1] : 0) + carry;
+    if (i < n) off[i] = before + v - c;
+    carry += wsum[15];
     __syncthreads();
   }
-  int run = t == 0 ? 0 : sums[t - 1];
-  for (int i = lo; i < hi; ++i) {
-    off[i] = run;
-    run += counts[i];
-  }
-  if (t == 1023) off[n] = sums[1023];
+  if (t == 0) off[n] = carry;
 }
 
 __global__ void k_scatter(const PointRec* __restrict__ tmp, const int2* __restrict__ colrank,
@@ -179,48 +231,85 @@ __global__ void k_scatter(const PointRec* __restrict__ tmp, const int2* __restri
 }
 
 // ---------------------------------------------------------------------------
-// P1 / B1: rasterise into LDS rows, then r2c FFT along j2.
-// MODE_SPLAT: v = splat of normals (3 channels)         [forward]
+// P1 / B1: rasterise one channel into LDS rows, then r2c FFT along j2.
+// MODE_SPLAT: v_c = splat of normal component c        [forward, grid x3]
 // MODE_BWDH : H = s G + alpha W - Q delta_0 (1 channel)   [backward]
-// MODE_LOADV: v loaded from global (3 channels)         [spectral test hook]
-// MODE_VOUT : splat only, rows written to global v       [splat test hook]
+// MODE_LOADV: v_c loaded from global                     [spectral test hook]
+// MODE_VOUT : splat only, rows written to global v_c      [splat test hook]
 // ---------------------------------------------------------------------------
 enum { MODE_SPLAT = 0, MODE_BWDH = 1, MODE_LOADV = 2, MODE_VOUT = 3 };
 
 template <int RES, int MODE>
-__global__ __launch_bounds__(kBlock) void k_splat_r2c(const PointRec* __restrict__ sorted,
-                                                      const int* __restrict__ off,
-                                                      const float* __restrict__ gin,
-                                                      const BwdScalars* __restrict__ bs,
-                                                      const cf* __restrict__ tw, cf* __restrict__ out,
-                                                      float* __restrict__ vout) {
-  constexpr int M = RES / 2, H = M + 1, T = tile_lines(RES);
-  constexpr int C = MODE == MODE_BWDH ? 1 : 3;
-  constexpr int LS = lstride(M);
+__global__ __launch_bounds__(rows_block(RES)) void k_splat_r2c(const PointRec* __restrict__ sorted,
+                                                              const int* __restrict__ off,
+                                                              const float* __restrict__ gin,
+                                                              const BwdScalars* __restrict__ bs,
+                                                              const cf* __restrict__ tw, cf* __restrict__ out,
+                                                              float* __restrict__ vout) {
+  constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_block(RES);
+  constexpr int TPL = plan_TPL(M), E = plan_E(M), LS = lstride(M);
   constexpr int64_t N3 = (int64_t)RES * RES * RES;
-  __shared__ cf rows[C * T * LS];
+  __shared__ cf rows[TR * LS];
+  __shared__ cf stw[M];      // FFT table of length M
+  __shared__ cf rtw[M + 1];  // W_RES^k, k in [0, M], for the r2c post-processing
+  if constexpr (MODE != MODE_VOUT) {
+    stage_table<BR>(stw, tw + M, M);
+    stage_table<BR>(rtw, tw + RES, M + 1);
+  }
   float* rf = reinterpret_cast<float*>(rows);
-  const int tb = blockIdx.x % (RES / T);
-  const int j0 = blockIdx.x / (RES / T);
-  const int a0 = tb * T;
+  int b = blockIdx.x;
+  const int tb = b % NT;
+  b /= NT;
+  const int j0 = b % RES;
+  const int c = b / RES;
+  const int a0 = tb * TR;
+  const int t = threadIdx.x;
+  int lo[4], hi[4], nr = 0, total = 0;
+  if constexpr (MODE != MODE_LOADV) {
+    nr = tile_ranges<RES>(off, j0, tb, lo, hi);
+    for (int r = 0; r < nr; ++r) total += hi[r] - lo[r];
+  }
+  if constexpr (MODE == MODE_SPLAT) {
+    // no point touches this tile: its rows and their spectra are zero
+    if (total == 0) {
+      for (int e = t; e < H * (TR / 2); e += BR) {
+        const int l = 2 * (e % (TR / 2)), k = e / (TR / 2);
+        *reinterpret_cast<float4*>(out + (((int64_t)c * H + k) * RES + j0) * RES + a0 + l) = make_float4(0, 0, 0, 0);
+      }
+      return;
+    }
+  }
 
   if constexpr (MODE == MODE_SPLAT || MODE == MODE_VOUT) {
-    for (int e = threadIdx.x; e < C * T * LS; e += kBlock) rows[e] = cf{0.0f, 0.0f};
+    for (int e = t; e < TR * LS; e += BR) rows[e] = cf{0.0f, 0.0f};
   } else {
     float sg = 1.0f, q = 0.0f;
     if constexpr (MODE == MODE_BWDH) {
       sg = bs->s;
       q = bs->q;
     }
-    for (int e = threadIdx.x; e < C * T * M; e += kBlock) {
-      const int mm = e % M, l = (e / M) % T, c = e / (M * T);
-      const int64_t gi = c * N3 + ((int64_t)j0 * RES + a0 + l) * RES + 2 * mm;
-      const float2 v = *reinterpret_cast<const float2*>(gin + gi);
-      cf z{v.x * sg, v.y * sg};
-      if constexpr (MODE == MODE_BWDH) {
-        if (j0 == 0 && a0 + l == 0 && mm == 0) z.x -= q;
+    // the TR rows of this tile are one contiguous run of TR * RES floats
+    constexpr int NV = TR * M / 2;  // float4 = two complex slots
+    constexpr int IT = (NV + BR - 1) / BR;
+    const float4* g4 = reinterpret_cast<const float4*>(gin + c * N3 + ((int64_t)j0 * RES + a0) * RES);
+    float4 buf[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * BR;
+      if (e < NV) buf[it] = g4[e];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * BR;
+      if (e < NV) {
+        const int mm = (2 * e) % M, l = (2 * e) / M;
+        cf z0{buf[it].x * sg, buf[it].y * sg}, z1{buf[it].z * sg, buf[it].w * sg};
+        if constexpr (MODE == MODE_BWDH) {
+          if (j0 == 0 && a0 + l == 0 && mm == 0) z0.x -= q;
+        }
+        rows[l * LS + pidx(mm)] = z0;
+        rows[l * LS + pidx(mm + 1)] = z1;
       }
-      rows[(c * T + l) * LS + pidx(mm)] = z;
     }
   }
 
@@ -228,17 +317,15 @@ __global__ __launch_bounds__(kBlock) void k_splat_r2c(const PointRec* __restrict
     float alpha = 0.0f;
     if constexpr (MODE == MODE_BWDH) alpha = bs->alpha;
     __syncthreads();
-    int lo[4], hi[4];
-    const int nr = tile_ranges<RES, T>(off, j0, a0, lo, hi);
-    int total = 0;
-    for (int r = 0; r < nr; ++r) total += hi[r] - lo[r];
-    for (int qd = threadIdx.x; qd < total; qd += kBlock) {
+    for (int qd = t; qd < total; qd += BR) {
       const int64_t s = range_pick(lo, hi, nr, qd);
       float4 p0, p1;
       load_rec(sorted, s, p0, p1);
       const uint32_t bb = __float_as_uint(p0.w);
       const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
-      const float nv[3] = {p1.x, p1.y, p1.z};
+      float val;
+      if constexpr (MODE == MODE_BWDH) val = alpha;
+      else val = c == 0 ? p1.x : (c == 1 ? p1.y : p1.z);
 #pragma unroll
       for (int o0 = 0; o0 < 2; ++o0) {
         if (((b0 + o0) & (RES - 1)) != j0) continue;
@@ -246,19 +333,13 @@ __global__ __launch_bounds__(kBlock) void k_splat_r2c(const PointRec* __restrict
 #pragma unroll
         for (int o1 = 0; o1 < 2; ++o1) {
           const int l = (b1 + o1 - a0) & (RES - 1);
-          if (l >= T) continue;
+          if (l >= TR) continue;
           const float w01 = w0 * (o1 ? p0.y : 1.0f - p0.y);
 #pragma unroll
           for (int o2 = 0; o2 < 2; ++o2) {
             const int nn = (b2 + o2) & (RES - 1);
             const float w = w01 * (o2 ? p0.z : 1.0f - p0.z);
-            const int addr = 2 * pidx(nn >> 1) + (nn & 1);
-            if constexpr (MODE == MODE_BWDH) {
-              atomicAdd(&rf[l * LS * 2 + addr], w * alpha);
-            } else {
-#pragma unroll
-              for (int c = 0; c < 3; ++c) atomicAdd(&rf[(c * T + l) * LS * 2 + addr], w * nv[c]);
-            }
+            atomicAdd(&rf[l * LS * 2 + 2 * pidx(nn >> 1) + (nn & 1)], w * val);
           }
         }
       }
@@ -267,49 +348,106 @@ __global__ __launch_bounds__(kBlock) void k_splat_r2c(const PointRec* __restrict
   __syncthreads();
 
   if constexpr (MODE == MODE_VOUT) {
-    for (int e = threadIdx.x; e < C * T * RES; e += kBlock) {
-      const int nn = e % RES, l = (e / RES) % T, c = e / (RES * T);
-      vout[c * N3 + ((int64_t)j0 * RES + a0 + l) * RES + nn] = rf[(c * T + l) * LS * 2 + 2 * pidx(nn >> 1) + (nn & 1)];
+    for (int e = t; e < TR * RES; e += BR) {
+      const int nn = e % RES, l = e / RES;
+      vout[c * N3 + ((int64_t)j0 * RES + a0 + l) * RES + nn] = rf[l * LS * 2 + 2 * pidx(nn >> 1) + (nn & 1)];
     }
-    return;
   } else {
-    fft_lines<M, -1>(rows, C * T, LS, tw + M);
-    const cf* twr = tw + RES;
-    for (int e = threadIdx.x; e < C * H * T; e += kBlock) {
-      const int l = e % T, k = (e / T) % H, c = e / (T * H);
-      const cf* row = rows + (c * T + l) * LS;
-      const cf zk = row[pidx(k == M ? 0 : k)];
-      const cf zm = row[pidx(k == 0 ? 0 : M - k)];
-      const cf E{0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)};
-      const cf O{0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x)};
-      const cf X = cadd(E, cmul(twr[k], O));
-      out[(((int64_t)c * H + k) * RES + j0) * RES + a0 + l] = X;
+    {
+      cf reg[E];
+      const int l = t / TPL;
+      fft<M, -1, false, false>(reg, rows + l * LS, t % TPL, stw);
+    }
+    // X[k] = E_k + W_r^k O_k with E = (Z_k + Z*_{M-k})/2, O = (Z_k - Z*_{M-k})/(2i)
+    for (int e = t; e < H * (TR / 2); e += BR) {
+      const int l = 2 * (e % (TR / 2)), k = e / (TR / 2);
+      const cf w = rtw[k];
+      float4 o;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const cf* row = rows + (l + h) * LS;
+        const cf zk = row[pidx(k == M ? 0 : k)];
+        const cf zm = row[pidx(k == 0 ? 0 : M - k)];
+        const cf Ee{0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)};
+        const cf Oo{0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x)};
+        const cf X = cadd(Ee, cmul(w, Oo));
+        if (h == 0) {
+          o.x = X.x;
+          o.y = X.y;
+        } else {
+          o.z = X.x;
+          o.w = X.y;
+        }
+      }
+      *reinterpret_cast<float4*>(out + (((int64_t)c * H + k) * RES + j0) * RES + a0 + l) = o;
     }
   }
 }
 
-// ---------------------------------------------------------------------------
-// P2 / B2: forward FFT along j1. A[c][k2][j0][j1] -> B[c][k1][k2][j0].
-// ---------------------------------------------------------------------------
+// Store the canonical registers of TC lines transposed: out[n][a0 + l] for
+// every element n of every line l, two lines per 16-byte store.
 template <int RES>
-__global__ __launch_bounds__(kBlock) void k_axis1_fwd(const cf* __restrict__ in, cf* __restrict__ out,
-                                                      const cf* __restrict__ tw) {
-  constexpr int H = RES / 2 + 1, T = tile_lines(RES), LS = lstride(RES);
-  __shared__ cf rows[T * LS];
-  int b = blockIdx.x;
-  const int tb = b % (RES / T);
-  b /= RES / T;
-  const int k2 = b % H;
-  const int c = b / H;
-  const int a0 = tb * T;
-  const cf* src = in + (((int64_t)c * H + k2) * RES + a0) * RES;
-  for (int e = threadIdx.x; e < T * RES; e += kBlock) rows[(e / RES) * LS + pidx(e % RES)] = src[e];
+__device__ __forceinline__ void store_transposed(cf* rows, const cf* reg, cf* __restrict__ dst, int64_t stride_n,
+                                                 int l, int lt) {
+  constexpr int TC = tile_cols(RES), BC = cols_block(RES), TPL = plan_TPL(RES), E = plan_E(RES),
+                LS = lstride(RES);
+#pragma unroll
+  for (int v = 0; v < E; ++v) rows[l * LS + pidx(lt + TPL * v)] = reg[v];
   __syncthreads();
-  fft_lines<RES, -1>(rows, T, LS, tw + RES);
-  for (int e = threadIdx.x; e < T * RES; e += kBlock) {
-    const int l = e % T, n = e / T;
-    out[(((int64_t)c * RES + n) * H + k2) * RES + a0 + l] = rows[l * LS + pidx(n)];
+  for (int e = threadIdx.x; e < RES * (TC / 2); e += BC) {
+    const int l2 = 2 * (e % (TC / 2)), n = e / (TC / 2);
+    const cf x0 = rows[l2 * LS + pidx(n)], x1 = rows[(l2 + 1) * LS + pidx(n)];
+    *reinterpret_cast<float4*>(dst + n * stride_n + l2) = make_float4(x0.x, x0.y, x1.x, x1.y);
   }
+}
+
+// ---------------------------------------------------------------------------
+// P2 / B2: forward FFT along j1. A[c][k2][j0][j1] -> B[c'][k1][k2][j0].
+// MERGE = false (B2): one channel in, one out.
+// MERGE = true (P2): three channels in, two out: v~_0, and
+//   W = kappa_1(k1) v~_1 + kappa_2(k2) v~_2, which is all the j0 pass needs of
+//   channels 1 and 2 because their operator factors do not vary along j0.
+// ---------------------------------------------------------------------------
+template <int RES, bool MERGE>
+__global__ __launch_bounds__(cols_block(RES)) void k_axis1_fwd(const cf* __restrict__ in, cf* __restrict__ out,
+                                                               const cf* __restrict__ tw) {
+  constexpr int H = RES / 2 + 1, TC = tile_cols(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
+  constexpr int64_t CH = (int64_t)H * RES * RES;  // elements per channel
+  __shared__ cf rows[TC * LS];
+  __shared__ cf stw[RES];
+  stage_table<cols_block(RES)>(stw, tw + RES, RES);
+  int b = blockIdx.x;
+  const int tb = b % (RES / TC);
+  b /= RES / TC;
+  const int k2 = b % H;
+  const int c = b / H;  // output channel
+  const int a0 = tb * TC;
+  const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
+  const cf* src = in + ((int64_t)k2 * RES + a0 + l) * RES;
+  cf reg[E];
+  if (!MERGE || c == 0) {
+#pragma unroll
+    for (int v = 0; v < E; ++v) reg[v] = src[c * CH + lt + TPL * v];
+    fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
+  } else {
+    cf acc[E];
+#pragma unroll
+    for (int v = 0; v < E; ++v) reg[v] = src[2 * CH + lt + TPL * v];
+    fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
+    const float k2f = kappa_odd(k2, RES);
+#pragma unroll
+    for (int v = 0; v < E; ++v) {
+      acc[v] = cf{k2f * reg[v].x, k2f * reg[v].y};
+      reg[v] = src[CH + lt + TPL * v];
+    }
+    fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
+#pragma unroll
+    for (int v = 0; v < E; ++v) {
+      const float k1f = kappa_odd(lt + TPL * v, RES);
+      reg[v] = cf{acc[v].x + k1f * reg[v].x, acc[v].y + k1f * reg[v].y};
+    }
+  }
+  store_transposed<RES>(rows, reg, out + ((int64_t)c * RES * H + k2) * RES + a0, (int64_t)H * RES, l, lt);
 }
 
 // ---------------------------------------------------------------------------
@@ -317,175 +455,235 @@ __global__ __launch_bounds__(kBlock) void k_axis1_fwd(const cf* __restrict__ in,
 // with F = g / (-2 pi |kappa|^2) / N (main Eq. 3; the inverse's 1/N folded
 // in), then inverse FFT along k0. B[3][k1][k2][j0] -> C[j0][k2][k1].
 // ---------------------------------------------------------------------------
-template <int RES>
-__device__ __forceinline__ float spectral_F(int k0, int k1, int k2, float sigma) {
-  const float q0 = kappa_of(k0, RES), q1 = kappa_of(k1, RES), q2 = kappa_of(k2, RES);
-  const float K2 = q0 * q0 + q1 * q1 + q2 * q2;
-  if (K2 == 0.0f) return 0.0f;
-  constexpr float invN = 1.0f / ((float)RES * (float)RES * (float)RES);
+// Separable Gaussian of main Eq. 3: g(k) = g1(k0) g1(k1) g1(k2) with
+// g1(k) = exp(-2 sigma^2 kappa(k)^2 / r^2); one table of RES floats per
+// workgroup in LDS (the Nyquist index keeps kappa^2 = (r/2)^2).
+template <int RES, int BLOCK>
+__device__ __forceinline__ void gauss_table(float* g1, float sigma) {
   constexpr float inv_r2 = 1.0f / ((float)RES * (float)RES);
-  const float g = expf(-2.0f * sigma * sigma * K2 * inv_r2);
-  return g * invN / (-6.283185307179586f * K2);
-}
-
-template <int RES>
-__global__ __launch_bounds__(kBlock) void k_fwd_axis0(const cf* __restrict__ in, cf* __restrict__ out,
-                                                      const cf* __restrict__ tw, float sigma) {
-  constexpr int H = RES / 2 + 1, T = tile_lines(RES), LS = lstride(RES);
-  constexpr int EPT = (T * RES + kBlock - 1) / kBlock;
-  __shared__ cf rows[T * LS];
-  const int tb = blockIdx.x % (RES / T);
-  const int k2 = blockIdx.x / (RES / T);
-  const int a0 = tb * T;
-  cf acc[EPT];
-#pragma unroll
-  for (int u = 0; u < EPT; ++u) acc[u] = cf{0.0f, 0.0f};
-  for (int c = 0; c < 3; ++c) {
-    for (int e = threadIdx.x; e < T * RES; e += kBlock) {
-      const int l = e / RES, n = e % RES;
-      rows[l * LS + pidx(n)] = in[(((int64_t)c * RES + a0 + l) * H + k2) * RES + n];
-    }
-    __syncthreads();
-    fft_lines<RES, -1>(rows, T, LS, tw + RES);
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int e = threadIdx.x + u * kBlock;
-      if (e < T * RES) {
-        const int l = e / RES, n = e % RES;
-        const float kap = c == 0 ? kappa_odd(n, RES) : (c == 1 ? kappa_odd(a0 + l, RES) : kappa_odd(k2, RES));
-        const cf x = rows[l * LS + pidx(n)];
-        acc[u].x += kap * x.x;
-        acc[u].y += kap * x.y;
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < EPT; ++u) {
-    const int e = threadIdx.x + u * kBlock;
-    if (e < T * RES) {
-      const int l = e / RES, n = e % RES;
-      const float F = spectral_F<RES>(n, a0 + l, k2, sigma);
-      rows[l * LS + pidx(n)] = cf{-F * acc[u].y, F * acc[u].x};  // i F acc
-    }
-  }
-  __syncthreads();
-  fft_lines<RES, +1>(rows, T, LS, tw + RES);
-  for (int e = threadIdx.x; e < T * RES; e += kBlock) {
-    const int l = e % T, n = e / T;
-    out[((int64_t)n * H + k2) * RES + a0 + l] = rows[l * LS + pidx(n)];
+  for (int e = threadIdx.x; e < RES; e += BLOCK) {
+    const float q = kappa_of(e, RES);
+    g1[e] = expf(-2.0f * sigma * sigma * q * q * inv_r2);
   }
 }
 
-// B3: FFT along j0 of H^, then for each channel d: -i F kappa_d H^ (the
-// conjugate operator), inverse FFT along k0. B[k1][k2][j0] -> C[3][j0][k2][k1].
+// F(k) = g(k) / (-2 pi |kappa|^2) / N, and 0 at k = 0 (the inverse's 1/N folded in).
 template <int RES>
-__global__ __launch_bounds__(kBlock) void k_bwd_axis0(const cf* __restrict__ in, cf* __restrict__ out,
-                                                      const cf* __restrict__ tw, float sigma) {
-  constexpr int H = RES / 2 + 1, T = tile_lines(RES), LS = lstride(RES);
-  constexpr int EPT = (T * RES + kBlock - 1) / kBlock;
-  __shared__ cf rows[T * LS];
-  const int tb = blockIdx.x % (RES / T);
-  const int k2 = blockIdx.x / (RES / T);
-  const int a0 = tb * T;
-  for (int e = threadIdx.x; e < T * RES; e += kBlock) {
-    const int l = e / RES, n = e % RES;
-    rows[l * LS + pidx(n)] = in[(((int64_t)a0 + l) * H + k2) * RES + n];
-  }
-  __syncthreads();
-  fft_lines<RES, -1>(rows, T, LS, tw + RES);
-  cf h[EPT];
-  float F[EPT];
+__device__ __forceinline__ float spectral_F(const float* g1, int k0, float g12, float q12) {
+  const float q0 = kappa_of(k0, RES);
+  const float K2 = q0 * q0 + q12;
+  constexpr float c = -1.0f / (6.283185307179586f * (float)RES * (float)RES * (float)RES);
+  return K2 == 0.0f ? 0.0f : g1[k0] * g12 * c / K2;
+}
+
+template <int RES>
+__global__ __launch_bounds__(cols_block(RES)) void k_fwd_axis0(const cf* __restrict__ in, cf* __restrict__ out,
+                                                               const cf* __restrict__ tw, float sigma) {
+  constexpr int H = RES / 2 + 1, TC = tile_cols(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
+  __shared__ cf rows[TC * LS];
+  __shared__ cf stw[RES];
+  __shared__ float g1[RES];
+  stage_table<cols_block(RES)>(stw, tw + RES, RES);
+  gauss_table<RES, cols_block(RES)>(g1, sigma);
+  const int tb = blockIdx.x % (RES / TC);
+  const int k2 = blockIdx.x / (RES / TC);
+  const int a0 = tb * TC;
+  const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
+  const int k1 = a0 + l;
+  const cf* src = in + ((int64_t)k1 * H + k2) * RES;
+  cf acc[E], reg[E];
+  // sum_d kappa_d v~_d = kappa_0(k0) FFT_j0(v~_0) + FFT_j0(W)
 #pragma unroll
-  for (int u = 0; u < EPT; ++u) {
-    const int e = threadIdx.x + u * kBlock;
-    if (e < T * RES) {
-      const int l = e / RES, n = e % RES;
-      h[u] = rows[l * LS + pidx(n)];
-      F[u] = spectral_F<RES>(n, a0 + l, k2, sigma);
-    }
-  }
-  __syncthreads();
-  for (int c = 0; c < 3; ++c) {
+  for (int v = 0; v < E; ++v) reg[v] = src[lt + TPL * v];
+  fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-      const int e = threadIdx.x + u * kBlock;
-      if (e < T * RES) {
-        const int l = e / RES, n = e % RES;
-        const float kap = c == 0 ? kappa_odd(n, RES) : (c == 1 ? kappa_odd(a0 + l, RES) : kappa_odd(k2, RES));
-        const float fk = F[u] * kap;
-        rows[l * LS + pidx(n)] = cf{fk * h[u].y, -fk * h[u].x};  // -i F kappa H^
-      }
-    }
-    __syncthreads();
-    fft_lines<RES, +1>(rows, T, LS, tw + RES);
-    for (int e = threadIdx.x; e < T * RES; e += kBlock) {
-      const int l = e % T, n = e / T;
-      out[(((int64_t)c * RES + n) * H + k2) * RES + a0 + l] = rows[l * LS + pidx(n)];
-    }
-    __syncthreads();
+  for (int v = 0; v < E; ++v) {
+    const float k0f = kappa_odd(lt + TPL * v, RES);
+    acc[v] = cf{k0f * reg[v].x, k0f * reg[v].y};
+    reg[v] = src[(int64_t)RES * H * RES + lt + TPL * v];
   }
+  fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
+  {
+    const float g12 = g1[k1] * g1[k2];
+    const float q12 = kappa_of(k1, RES) * kappa_of(k1, RES) + kappa_of(k2, RES) * kappa_of(k2, RES);
+#pragma unroll
+    for (int v = 0; v < E; ++v) {
+      const float F = spectral_F<RES>(g1, lt + TPL * v, g12, q12);
+      const cf a{acc[v].x + reg[v].x, acc[v].y + reg[v].y};
+      reg[v] = cf{-F * a.y, F * a.x};  // i F sum
+    }
+  }
+  fft<RES, +1, true, true>(reg, rows + l * LS, lt, stw);
+  store_transposed<RES>(rows, reg, out + (int64_t)k2 * RES + a0, (int64_t)H * RES, l, lt);
+}
+
+// B3: FFT along j0 of H^, then the conjugate operator -i F kappa_d H^ and the
+// inverse FFT along k0. Channel 0 carries kappa_0(k0); channels 1 and 2 only
+// differ by the constants kappa_1(k1), kappa_2(k2) along the line, so one
+// unscaled channel U = IFFT_k0(-i F H^) serves both (kappa_1 is applied in
+// the k1 pass, kappa_2 in the k2 pass). B[k1][k2][j0] -> C[2][j0][k2][k1].
+template <int RES>
+__global__ __launch_bounds__(cols_block(RES)) void k_bwd_axis0(const cf* __restrict__ in, cf* __restrict__ out,
+                                                               const cf* __restrict__ tw, float sigma) {
+  constexpr int H = RES / 2 + 1, TC = tile_cols(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
+  __shared__ cf rows[TC * LS];
+  __shared__ cf stw[RES];
+  __shared__ float g1[RES];
+  stage_table<cols_block(RES)>(stw, tw + RES, RES);
+  gauss_table<RES, cols_block(RES)>(g1, sigma);
+  const int tb = blockIdx.x % (RES / TC);
+  const int k2 = blockIdx.x / (RES / TC);
+  const int a0 = tb * TC;
+  const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
+  const int k1 = a0 + l;
+  const cf* src = in + ((int64_t)k1 * H + k2) * RES;
+  cf h[E], reg[E];
+#pragma unroll
+  for (int v = 0; v < E; ++v) h[v] = src[lt + TPL * v];
+  fft<RES, -1, true, true>(h, rows + l * LS, lt, stw);
+  const float g12 = g1[k1] * g1[k2];
+  const float q12 = kappa_of(k1, RES) * kappa_of(k1, RES) + kappa_of(k2, RES) * kappa_of(k2, RES);
+#pragma unroll
+  for (int v = 0; v < E; ++v) {
+    const float F = spectral_F<RES>(g1, lt + TPL * v, g12, q12);
+    h[v] = cf{F * h[v].y, -F * h[v].x};  // -i F H^
+    const float k0f = kappa_odd(lt + TPL * v, RES);
+    reg[v] = cf{k0f * h[v].x, k0f * h[v].y};
+  }
+  fft<RES, +1, true, true>(reg, rows + l * LS, lt, stw);
+  store_transposed<RES>(rows, reg, out + (int64_t)k2 * RES + a0, (int64_t)H * RES, l, lt);
+  __syncthreads();
+  fft<RES, +1, true, true>(h, rows + l * LS, lt, stw);
+  store_transposed<RES>(rows, h, out + ((int64_t)RES * H + k2) * RES + a0, (int64_t)H * RES, l, lt);
 }
 
 // ---------------------------------------------------------------------------
-// P4 / B4: inverse FFT along k1. C[c][j0][k2][k1] -> D[c][k2][j0][j1].
+// P4 / B4: inverse FFT along k1. C[c][j0][k2][k1] -> D[c'][k2][j0][j1].
+// SPLIT = false (P4): one channel in, one out.
+// SPLIT = true (B4): channels (V0, U) in, three out: IFFT(V0),
+//   IFFT(kappa_1(k1) U) and IFFT(U) (the last still lacks kappa_2(k2), which
+//   the c2r pass applies).
 // ---------------------------------------------------------------------------
-template <int RES>
-__global__ __launch_bounds__(kBlock) void k_axis1_inv(const cf* __restrict__ in, cf* __restrict__ out,
-                                                      const cf* __restrict__ tw) {
-  constexpr int H = RES / 2 + 1, T = tile_lines(RES), LS = lstride(RES);
-  __shared__ cf rows[T * LS];
+template <int RES, bool SPLIT>
+__global__ __launch_bounds__(cols_block(RES)) void k_axis1_inv(const cf* __restrict__ in, cf* __restrict__ out,
+                                                               const cf* __restrict__ tw) {
+  constexpr int H = RES / 2 + 1, TC = tile_cols(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
+  constexpr int64_t CH = (int64_t)H * RES * RES;
+  __shared__ cf rows[TC * LS];
+  __shared__ cf stw[RES];
+  stage_table<cols_block(RES)>(stw, tw + RES, RES);
   int b = blockIdx.x;
-  const int tb = b % (RES / T);
-  b /= RES / T;
+  const int tb = b % (RES / TC);
+  b /= RES / TC;
   const int k2 = b % H;
-  const int c = b / H;
-  const int a0 = tb * T;
-  for (int e = threadIdx.x; e < T * RES; e += kBlock) {
-    const int l = e / RES, n = e % RES;
-    rows[l * LS + pidx(n)] = in[(((int64_t)c * RES + a0 + l) * H + k2) * RES + n];
+  const int c = b / H;  // input channel
+  const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
+  const int j0 = tb * TC + l;
+  const cf* src = in + c * CH + ((int64_t)j0 * H + k2) * RES;
+  cf* dst = out + c * CH + ((int64_t)k2 * RES + j0) * RES;
+  cf reg[E];
+  if (!SPLIT || c == 0) {
+#pragma unroll
+    for (int v = 0; v < E; ++v) reg[v] = src[lt + TPL * v];
+    fft<RES, +1, true, true>(reg, rows + l * LS, lt, stw);
+#pragma unroll
+    for (int v = 0; v < E; ++v) dst[lt + TPL * v] = reg[v];
+  } else {
+    cf u[E];
+#pragma unroll
+    for (int v = 0; v < E; ++v) {
+      u[v] = src[lt + TPL * v];
+      const float k1f = kappa_odd(lt + TPL * v, RES);
+      reg[v] = cf{k1f * u[v].x, k1f * u[v].y};
+    }
+    fft<RES, +1, true, true>(reg, rows + l * LS, lt, stw);
+#pragma unroll
+    for (int v = 0; v < E; ++v) dst[lt + TPL * v] = reg[v];
+    fft<RES, +1, true, true>(u, rows + l * LS, lt, stw);
+#pragma unroll
+    for (int v = 0; v < E; ++v) dst[CH + lt + TPL * v] = u[v];
   }
-  __syncthreads();
-  fft_lines<RES, +1>(rows, T, LS, tw + RES);
-  cf* dst = out + (((int64_t)c * H + k2) * RES + a0) * RES;
-  for (int e = threadIdx.x; e < T * RES; e += kBlock) dst[e] = rows[(e / RES) * LS + pidx(e % RES)];
 }
 
 // ---------------------------------------------------------------------------
-// P5 / B5: complex-to-real inverse FFT along k2 of a tile of lines, then the
-// trilinear gather at the points whose corner lines fall in the tile.
-// MODE_FWD: 1 channel; writes chi' rows and per (point, corner-line) partials
-//           (value, d/dc0, d/dc1, d/dc2) of the interpolant.
-// MODE_BWD: 3 channels g_v; partials of dL/dn (3) and dL/dc (3).
-// MODE_DBG: 1 channel; writes chi' rows only.
+// P5 / B5: complex-to-real inverse FFT along k2 of a row tile of one channel,
+// then the trilinear gather at the points whose corner lines fall in the tile.
+// Per (point, corner line, channel) the partial is (value, d/dc0, d/dc1,
+// d/dc2) of the interpolant restricted to that line.
+// MODE_FWD: chi' (1 channel): writes chi' rows and the partials.
+// MODE_BWD: g_v channel c (grid x3): partials only.
+// MODE_DBG: chi' rows only.
 // ---------------------------------------------------------------------------
 enum { MODE_FWD = 0, MODE_BWD = 1, MODE_DBG = 2 };
 
 template <int RES, int MODE>
-__global__ __launch_bounds__(kBlock) void k_c2r_gather(const cf* __restrict__ in, float* __restrict__ chi_out,
-                                                       const PointRec* __restrict__ sorted,
-                                                       const int* __restrict__ off, float4* __restrict__ part,
-                                                       const cf* __restrict__ tw) {
-  constexpr int M = RES / 2, H = M + 1, T = tile_lines(RES);
-  constexpr int C = MODE == MODE_BWD ? 3 : 1;
-  constexpr int LS = lstride(M);
-  __shared__ cf rows[C * T * LS];
+__global__ __launch_bounds__(rows_block(RES)) void k_c2r_gather(const cf* __restrict__ in,
+                                                               float* __restrict__ chi_out,
+                                                               const PointRec* __restrict__ sorted,
+                                                               const int* __restrict__ off,
+                                                               float4* __restrict__ part,
+                                                               const cf* __restrict__ tw) {
+  constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_block(RES);
+  constexpr int TPL = plan_TPL(M), E = plan_E(M), LS = lstride(M);
+  __shared__ cf rows[TR * LS];
+  __shared__ cf stw[M];      // FFT table of length M
+  __shared__ cf rtw[M + 1];  // W_RES^k, k in [0, M], for the c2r pre-processing
+  stage_table<BR>(stw, tw + M, M);
+  stage_table<BR>(rtw, tw + RES, M + 1);
   const float* rf = reinterpret_cast<const float*>(rows);
-  const int tb = blockIdx.x % (RES / T);
-  const int j0 = blockIdx.x / (RES / T);
-  const int a0 = tb * T;
+  int b = blockIdx.x;
+  const int tb = b % NT;
+  b /= NT;
+  const int j0 = b % RES;
+  const int c = b / RES;
+  const int a0 = tb * TR;
+  const int t = threadIdx.x;
+  int lo[4], hi[4], nr = 0, total = 0;
+  if constexpr (MODE != MODE_DBG) {
+    nr = tile_ranges<RES>(off, j0, tb, lo, hi);
+    for (int r = 0; r < nr; ++r) total += hi[r] - lo[r];
+    // the backward pass only produces per-point partials: a tile that no
+    // point touches has nothing to do (uniform across the workgroup)
+    if (MODE == MODE_BWD && total == 0) return;
+  }
 
-  for (int e = threadIdx.x; e < C * H * T; e += kBlock) {
-    const int l = e % T, k = (e / T) % H, c = e / (T * H);
-    rows[(c * T + l) * LS + pidx(k)] = in[(((int64_t)c * H + k) * RES + j0) * RES + a0 + l];
+  {
+    constexpr int NV = H * (TR / 2);
+    constexpr int IT = (NV + BR - 1) / BR;
+    float4 buf[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * BR;
+      if (e < NV) {
+        const int l = 2 * (e % (TR / 2)), k = e / (TR / 2);
+        buf[it] = *reinterpret_cast<const float4*>(in + (((int64_t)c * H + k) * RES + j0) * RES + a0 + l);
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * BR;
+      if (e < NV) {
+        const int l = 2 * (e % (TR / 2)), k = e / (TR / 2);
+        float4 v = buf[it];
+        if (MODE == MODE_BWD && c == 2) {  // channel 2 still lacks its kappa_2(k2) factor
+          const float k2f = kappa_odd(k, RES);
+          v.x *= k2f;
+          v.y *= k2f;
+          v.z *= k2f;
+          v.w *= k2f;
+        }
+        rows[l * LS + pidx(k)] = cf{v.x, v.y};
+        rows[(l + 1) * LS + pidx(k)] = cf{v.z, v.w};
+      }
+    }
   }
   __syncthreads();
   // Hermitian half-spectrum X[0..M] -> packed spectrum Z[0..M) of the
   // even/odd samples: Z = (X_k + X*_{M-k}) + i (X_k - X*_{M-k}) e^{+2 pi i k/r}.
   {
     constexpr int NP = M / 2 + 1;
-    const cf* twr = tw + RES;
-    for (int e = threadIdx.x; e < C * T * NP; e += kBlock) {
+    const cf* twr = rtw;
+    for (int e = t; e < TR * NP; e += BR) {
       const int k = e % NP, row = e / NP;
       cf* rp = rows + row * LS;
       const cf xk = rp[pidx(k)], xm = rp[pidx(M - k)];
@@ -506,20 +704,20 @@ __global__ __launch_bounds__(kBlock) void k_c2r_gather(const cf* __restrict__ in
     }
   }
   __syncthreads();
-  fft_lines<M, +1>(rows, C * T, LS, tw + M);
+  {
+    cf reg[E];
+    fft<M, +1, false, false>(reg, rows + (t / TPL) * LS, t % TPL, stw);
+  }
   // rows now hold real lines, sample n at float slot 2 pidx(n/2) + (n&1)
   if constexpr (MODE != MODE_BWD) {
-    for (int e = threadIdx.x; e < T * RES; e += kBlock) {
-      const int l = e / RES, n = e % RES;
-      chi_out[((int64_t)j0 * RES + a0 + l) * RES + n] = rf[l * LS * 2 + 2 * pidx(n >> 1) + (n & 1)];
+    for (int e = t; e < TR * M; e += BR) {
+      const int l = e / M, mm = e % M;
+      const cf z = rows[l * LS + pidx(mm)];
+      *reinterpret_cast<float2*>(chi_out + ((int64_t)j0 * RES + a0 + l) * RES + 2 * mm) = make_float2(z.x, z.y);
     }
   }
   if constexpr (MODE != MODE_DBG) {
-    int lo[4], hi[4];
-    const int nr = tile_ranges<RES, T>(off, j0, a0, lo, hi);
-    int total = 0;
-    for (int r = 0; r < nr; ++r) total += hi[r] - lo[r];
-    for (int qd = threadIdx.x; qd < total; qd += kBlock) {
+    for (int qd = t; qd < total; qd += BR) {
       const int64_t s = range_pick(lo, hi, nr, qd);
       float4 p0, p1;
       load_rec(sorted, s, p0, p1);
@@ -536,30 +734,17 @@ __global__ __launch_bounds__(kBlock) void k_c2r_gather(const cf* __restrict__ in
 #pragma unroll
         for (int o1 = 0; o1 < 2; ++o1) {
           const int l = (b1 + o1 - a0) & (RES - 1);
-          if (l >= T) continue;
+          if (l >= TR) continue;
           const float wb = o1 ? p0.y : 1.0f - p0.y;
           const float sb = o1 ? 1.0f : -1.0f;
+          const float v0 = rf[l * LS * 2 + s0], v1 = rf[l * LS * 2 + s1];
+          const float L = (1.0f - fz) * v0 + fz * v1;
+          const float dL = v1 - v0;
+          const float4 q = make_float4(wa * wb * L, (float)RES * sa * wb * L, (float)RES * wa * sb * L,
+                                       (float)RES * wa * wb * dL);
           const int slot = o0 * 2 + o1;
-          if constexpr (MODE == MODE_FWD) {
-            const float v0 = rf[l * LS * 2 + s0], v1 = rf[l * LS * 2 + s1];
-            const float L = (1.0f - fz) * v0 + fz * v1;
-            const float dL = v1 - v0;
-            part[s * 4 + slot] = make_float4(wa * wb * L, (float)RES * sa * wb * L, (float)RES * wa * sb * L,
-                                             (float)RES * wa * wb * dL);
-          } else {
-            float Lc[3], dLc[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const float v0 = rf[(c * T + l) * LS * 2 + s0], v1 = rf[(c * T + l) * LS * 2 + s1];
-              Lc[c] = (1.0f - fz) * v0 + fz * v1;
-              dLc[c] = v1 - v0;
-            }
-            const float Ln = p1.x * Lc[0] + p1.y * Lc[1] + p1.z * Lc[2];
-            const float dLn = p1.x * dLc[0] + p1.y * dLc[1] + p1.z * dLc[2];
-            const float ww = wa * wb;
-            part[(s * 4 + slot) * 2 + 0] = make_float4(ww * Lc[0], ww * Lc[1], ww * Lc[2], (float)RES * sa * wb * Ln);
-            part[(s * 4 + slot) * 2 + 1] = make_float4((float)RES * wa * sb * Ln, (float)RES * ww * dLn, 0.0f, 0.0f);
-          }
+          if constexpr (MODE == MODE_FWD) part[s * 4 + slot] = q;
+          else part[(s * 4 + slot) * 3 + c] = q;
         }
       }
     }
@@ -583,7 +768,7 @@ __device__ __forceinline__ Tv block_sum(Tv v, Tv* sh) {
   return r;
 }
 
-// per point: f_i = sum of its 4 corner-line partials (FP64), grad f_i (FP32)
+// Per point: f_i = sum of its 4 corner-line partials (FP64), grad f_i (FP32).
 __global__ __launch_bounds__(256) void k_fwd_point_reduce(const float4* __restrict__ part, int64_t npoints,
                                                           float4* __restrict__ gradf, double* __restrict__ blockpart) {
   __shared__ double sh[256];
@@ -599,6 +784,8 @@ __global__ __launch_bounds__(256) void k_fwd_point_reduce(const float4* __restri
   if (threadIdx.x == 0) blockpart[blockIdx.x] = tot;
 }
 
+// mu = (1/P) sum_i f_i, c = chi'(0) - mu (reading B) or chi'(0) (reading A),
+// s = m/|c| (main Eq. 4), status; block partials summed in a fixed order.
 __global__ __launch_bounds__(256) void k_fwd_scalars(const double* __restrict__ blockpart, int nb,
                                                      const float* __restrict__ chi, SavedHeader* __restrict__ hdr) {
   __shared__ double sh[256];
@@ -633,7 +820,7 @@ __global__ void k_normalize(float* __restrict__ chi, int64_t n, const SavedHeade
   }
 }
 
-// backward: S_G = sum G, S_Gchi = sum G chi (FP64 partials per block)
+// Backward: S_G = sum G, S_Gchi = sum G chi (FP64 partials per block).
 __global__ __launch_bounds__(256) void k_bwd_reduce(const float* __restrict__ G, const float* __restrict__ chi,
                                                     int64_t n, double2* __restrict__ blockpart) {
   __shared__ double sh[256];
@@ -650,6 +837,7 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(const float* __restrict__ G,
   if (threadIdx.x == 0) blockpart[blockIdx.x] = make_double2(a, b);
 }
 
+// Q = S_Gchi / c, g_mu = -s S_G + Q (reading B; reading A drops Q), alpha = g_mu / P.
 __global__ __launch_bounds__(256) void k_bwd_scalars(const double2* __restrict__ blockpart, int nb,
                                                      const SavedHeader* __restrict__ hdr, BwdScalars* __restrict__ bs) {
   __shared__ double sh[256];
@@ -679,54 +867,70 @@ __global__ void k_bwd_point_finalize(const float4* __restrict__ part, const floa
                                      int64_t npoints, float* __restrict__ dpoints, float* __restrict__ dnormals) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= npoints) return;
-  float dn[3] = {0, 0, 0}, dc[3] = {0, 0, 0};
+  float4 p0, p1;
+  load_rec(sorted, s, p0, p1);
+  const float nv[3] = {p1.x, p1.y, p1.z};
+  float dn[3] = {0.0f, 0.0f, 0.0f}, dc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int slot = 0; slot < 4; ++slot) {
-    const float4 a = part[(s * 4 + slot) * 2 + 0], b = part[(s * 4 + slot) * 2 + 1];
-    dn[0] += a.x;
-    dn[1] += a.y;
-    dn[2] += a.z;
-    dc[0] += a.w;
-    dc[1] += b.x;
-    dc[2] += b.y;
+  for (int c = 0; c < 3; ++c) {
+    float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+#pragma unroll
+    for (int slot = 0; slot < 4; ++slot) {
+      const float4 q = part[(s * 4 + slot) * 3 + c];
+      dn[c] += q.x;
+      g0 += q.y;
+      g1 += q.z;
+      g2 += q.w;
+    }
+    dc[0] += nv[c] * g0;
+    dc[1] += nv[c] * g1;
+    dc[2] += nv[c] * g2;
   }
   const float alpha = bs->alpha;
   const float4 g = gradf[s];
   dc[0] += alpha * g.x;
   dc[1] += alpha * g.y;
   dc[2] += alpha * g.z;
-  const uint32_t i = sorted[s].idx;
+  const int64_t i = (int64_t)__float_as_uint(p1.w);
   if (dpoints) {
-    dpoints[3 * (int64_t)i + 0] = dc[0];
-    dpoints[3 * (int64_t)i + 1] = dc[1];
-    dpoints[3 * (int64_t)i + 2] = dc[2];
+    dpoints[3 * i + 0] = dc[0];
+    dpoints[3 * i + 1] = dc[1];
+    dpoints[3 * i + 2] = dc[2];
   }
   if (dnormals) {
-    dnormals[3 * (int64_t)i + 0] = dn[0];
-    dnormals[3 * (int64_t)i + 1] = dn[1];
-    dnormals[3 * (int64_t)i + 2] = dn[2];
+    dnormals[3 * i + 0] = dn[0];
+    dnormals[3 * i + 1] = dn[1];
+    dnormals[3 * i + 2] = dn[2];
   }
 }
 
 // ---------------------------------------------------------------------------
 // host-side launchers, one instantiation per resolution
 // ---------------------------------------------------------------------------
-#define PSR_CHECK_LAUNCH()                       \
-  do {                                           \
+#define PSR_CHECK_LAUNCH()                          \
+  do {                                              \
     if (hipGetLastError() != hipSuccess) return -4; \
   } while (0)
 
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 template <int RES>
+struct Grid {
+  static constexpr int H = RES / 2 + 1;
+  static constexpr int rows = RES * row_tiles(RES);      // row-pass workgroups per channel
+  static constexpr int cols = H * (RES / tile_cols(RES));  // column-pass workgroups per channel
+  static constexpr int BR = rows_block(RES), BC = cols_block(RES);
+};
+
+template <int RES>
 static int launch_bin(Exec& x, const float* pts, const float* nrm, int64_t P, const WsView& w, const SavedView& sv) {
-  constexpr int N2 = RES * RES;
+  constexpr int NB = num_bins(RES);
   x.begin(STAGE_BIN);
-  hipLaunchKernelGGL(k_init, dim3(nblk(N2, 256) > 1024 ? 1024 : nblk(N2, 256)), dim3(256), 0, x.stream, w.counts, N2,
+  hipLaunchKernelGGL(k_init, dim3(nblk(NB, 256) > 64 ? 64 : nblk(NB, 256)), dim3(256), 0, x.stream, w.counts, NB,
                      sv.hdr, RES, P, x.sigma, (float)x.m, x.reading);
-  hipLaunchKernelGGL(k_bin<RES>, dim3(nblk(P, 256)), dim3(256), 0, x.stream, pts, nrm, P, w.counts, w.tmp, w.colrank,
-                     sv.hdr);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, x.stream, w.counts, sv.off, N2);
+  hipLaunchKernelGGL(k_bin<RES>, dim3(nblk(P, kBinChunk)), dim3(256), 0, x.stream, pts, nrm, P, w.counts, w.tmp,
+                     w.colrank, sv.hdr);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, x.stream, w.counts, sv.off, NB);
   hipLaunchKernelGGL(k_scatter, dim3(nblk(P, 256)), dim3(256), 0, x.stream, w.tmp, w.colrank, sv.off, sv.sorted, P);
   x.end(STAGE_BIN);
   PSR_CHECK_LAUNCH();
@@ -736,25 +940,25 @@ static int launch_bin(Exec& x, const float* pts, const float* nrm, int64_t P, co
 template <int RES>
 static int launch_forward(Exec& x, const float* pts, const float* nrm, int64_t P, float* chi, const WsView& w,
                           const SavedView& sv) {
-  constexpr int H = RES / 2 + 1, T = tile_lines(RES);
+  using G = Grid<RES>;
   constexpr int64_t N3 = (int64_t)RES * RES * RES;
   if (int rc = launch_bin<RES>(x, pts, nrm, P, w, sv)) return rc;
   x.begin(STAGE_P1);
-  hipLaunchKernelGGL((k_splat_r2c<RES, MODE_SPLAT>), dim3(RES * (RES / T)), dim3(kBlock), 0, x.stream, sv.sorted,
-                     sv.off, (const float*)nullptr, (const BwdScalars*)nullptr, x.tw, w.X, (float*)nullptr);
+  hipLaunchKernelGGL((k_splat_r2c<RES, MODE_SPLAT>), dim3(3 * G::rows), dim3(G::BR), 0, x.stream, sv.sorted, sv.off,
+                     (const float*)nullptr, (const BwdScalars*)nullptr, x.tw, w.X, (float*)nullptr);
   x.end(STAGE_P1);
   x.begin(STAGE_P2);
-  hipLaunchKernelGGL(k_axis1_fwd<RES>, dim3(3 * H * (RES / T)), dim3(kBlock), 0, x.stream, w.X, w.Y, x.tw);
+  hipLaunchKernelGGL((k_axis1_fwd<RES, true>), dim3(2 * G::cols), dim3(G::BC), 0, x.stream, w.X, w.Y, x.tw);
   x.end(STAGE_P2);
   x.begin(STAGE_P3);
-  hipLaunchKernelGGL(k_fwd_axis0<RES>, dim3(H * (RES / T)), dim3(kBlock), 0, x.stream, w.Y, w.X, x.tw, x.sigma);
+  hipLaunchKernelGGL(k_fwd_axis0<RES>, dim3(G::cols), dim3(G::BC), 0, x.stream, w.Y, w.X, x.tw, x.sigma);
   x.end(STAGE_P3);
   x.begin(STAGE_P4);
-  hipLaunchKernelGGL(k_axis1_inv<RES>, dim3(H * (RES / T)), dim3(kBlock), 0, x.stream, w.X, w.Y, x.tw);
+  hipLaunchKernelGGL((k_axis1_inv<RES, false>), dim3(G::cols), dim3(G::BC), 0, x.stream, w.X, w.Y, x.tw);
   x.end(STAGE_P4);
   x.begin(STAGE_P5);
-  hipLaunchKernelGGL((k_c2r_gather<RES, MODE_FWD>), dim3(RES * (RES / T)), dim3(kBlock), 0, x.stream, w.Y, chi,
-                     sv.sorted, sv.off, w.part, x.tw);
+  hipLaunchKernelGGL((k_c2r_gather<RES, MODE_FWD>), dim3(G::rows), dim3(G::BR), 0, x.stream, w.Y, chi, sv.sorted,
+                     sv.off, w.part, x.tw);
   x.end(STAGE_P5);
   const int nb = nblk(P, 256) > kRedBlocks ? kRedBlocks : nblk(P, 256);
   x.begin(STAGE_FWD_REDUCE);
@@ -772,29 +976,29 @@ static int launch_forward(Exec& x, const float* pts, const float* nrm, int64_t P
 template <int RES>
 static int launch_backward(Exec& x, int64_t P, const float* chi, const float* dchi, float* dpts, float* dnrm,
                            const WsView& w, const SavedView& sv) {
-  constexpr int H = RES / 2 + 1, T = tile_lines(RES);
+  using G = Grid<RES>;
   constexpr int64_t N3 = (int64_t)RES * RES * RES;
-  const int nbr = kRedBlocks;
+  const int nbr = nblk(N3 / 4, 256) > kRedBlocks ? kRedBlocks : nblk(N3 / 4, 256);
   x.begin(STAGE_BWD_REDUCE);
   hipLaunchKernelGGL(k_bwd_reduce, dim3(nbr), dim3(256), 0, x.stream, dchi, chi, N3, (double2*)w.blockpart);
   hipLaunchKernelGGL(k_bwd_scalars, dim3(1), dim3(256), 0, x.stream, (const double2*)w.blockpart, nbr,
                      (const SavedHeader*)sv.hdr, w.bs);
   x.end(STAGE_BWD_REDUCE);
   x.begin(STAGE_B1);
-  hipLaunchKernelGGL((k_splat_r2c<RES, MODE_BWDH>), dim3(RES * (RES / T)), dim3(kBlock), 0, x.stream, sv.sorted,
-                     sv.off, dchi, (const BwdScalars*)w.bs, x.tw, w.X, (float*)nullptr);
+  hipLaunchKernelGGL((k_splat_r2c<RES, MODE_BWDH>), dim3(G::rows), dim3(G::BR), 0, x.stream, sv.sorted, sv.off, dchi,
+                     (const BwdScalars*)w.bs, x.tw, w.X, (float*)nullptr);
   x.end(STAGE_B1);
   x.begin(STAGE_B2);
-  hipLaunchKernelGGL(k_axis1_fwd<RES>, dim3(1 * H * (RES / T)), dim3(kBlock), 0, x.stream, w.X, w.Y, x.tw);
+  hipLaunchKernelGGL((k_axis1_fwd<RES, false>), dim3(G::cols), dim3(G::BC), 0, x.stream, w.X, w.Y, x.tw);
   x.end(STAGE_B2);
   x.begin(STAGE_B3);
-  hipLaunchKernelGGL(k_bwd_axis0<RES>, dim3(H * (RES / T)), dim3(kBlock), 0, x.stream, w.Y, w.X, x.tw, x.sigma);
+  hipLaunchKernelGGL(k_bwd_axis0<RES>, dim3(G::cols), dim3(G::BC), 0, x.stream, w.Y, w.X, x.tw, x.sigma);
   x.end(STAGE_B3);
   x.begin(STAGE_B4);
-  hipLaunchKernelGGL(k_axis1_inv<RES>, dim3(3 * H * (RES / T)), dim3(kBlock), 0, x.stream, w.X, w.Y, x.tw);
+  hipLaunchKernelGGL((k_axis1_inv<RES, true>), dim3(2 * G::cols), dim3(G::BC), 0, x.stream, w.X, w.Y, x.tw);
   x.end(STAGE_B4);
   x.begin(STAGE_B5);
-  hipLaunchKernelGGL((k_c2r_gather<RES, MODE_BWD>), dim3(RES * (RES / T)), dim3(kBlock), 0, x.stream, w.Y,
+  hipLaunchKernelGGL((k_c2r_gather<RES, MODE_BWD>), dim3(3 * G::rows), dim3(G::BR), 0, x.stream, w.Y,
                      (float*)nullptr, sv.sorted, sv.off, w.part, x.tw);
   x.end(STAGE_B5);
   x.begin(STAGE_BWD_FINAL);
@@ -807,15 +1011,15 @@ static int launch_backward(Exec& x, int64_t P, const float* chi, const float* dc
 
 template <int RES>
 static int launch_debug_spectral(Exec& x, const float* v, float* chi_prime, const WsView& w) {
-  constexpr int H = RES / 2 + 1, T = tile_lines(RES);
-  hipLaunchKernelGGL((k_splat_r2c<RES, MODE_LOADV>), dim3(RES * (RES / T)), dim3(kBlock), 0, x.stream,
+  using G = Grid<RES>;
+  hipLaunchKernelGGL((k_splat_r2c<RES, MODE_LOADV>), dim3(3 * G::rows), dim3(G::BR), 0, x.stream,
                      (const PointRec*)nullptr, (const int*)nullptr, v, (const BwdScalars*)nullptr, x.tw, w.X,
                      (float*)nullptr);
-  hipLaunchKernelGGL(k_axis1_fwd<RES>, dim3(3 * H * (RES / T)), dim3(kBlock), 0, x.stream, w.X, w.Y, x.tw);
-  hipLaunchKernelGGL(k_fwd_axis0<RES>, dim3(H * (RES / T)), dim3(kBlock), 0, x.stream, w.Y, w.X, x.tw, x.sigma);
-  hipLaunchKernelGGL(k_axis1_inv<RES>, dim3(H * (RES / T)), dim3(kBlock), 0, x.stream, w.X, w.Y, x.tw);
-  hipLaunchKernelGGL((k_c2r_gather<RES, MODE_DBG>), dim3(RES * (RES / T)), dim3(kBlock), 0, x.stream, w.Y,
-                     chi_prime, (const PointRec*)nullptr, (const int*)nullptr, (float4*)nullptr, x.tw);
+  hipLaunchKernelGGL((k_axis1_fwd<RES, true>), dim3(2 * G::cols), dim3(G::BC), 0, x.stream, w.X, w.Y, x.tw);
+  hipLaunchKernelGGL(k_fwd_axis0<RES>, dim3(G::cols), dim3(G::BC), 0, x.stream, w.Y, w.X, x.tw, x.sigma);
+  hipLaunchKernelGGL((k_axis1_inv<RES, false>), dim3(G::cols), dim3(G::BC), 0, x.stream, w.X, w.Y, x.tw);
+  hipLaunchKernelGGL((k_c2r_gather<RES, MODE_DBG>), dim3(G::rows), dim3(G::BR), 0, x.stream, w.Y, chi_prime,
+                     (const PointRec*)nullptr, (const int*)nullptr, (float4*)nullptr, x.tw);
   PSR_CHECK_LAUNCH();
   return 0;
 }
@@ -823,10 +1027,10 @@ static int launch_debug_spectral(Exec& x, const float* v, float* chi_prime, cons
 template <int RES>
 static int launch_debug_splat(Exec& x, const float* pts, const float* nrm, int64_t P, float* v, const WsView& w,
                               const SavedView& sv) {
-  constexpr int T = tile_lines(RES);
+  using G = Grid<RES>;
   if (int rc = launch_bin<RES>(x, pts, nrm, P, w, sv)) return rc;
-  hipLaunchKernelGGL((k_splat_r2c<RES, MODE_VOUT>), dim3(RES * (RES / T)), dim3(kBlock), 0, x.stream, sv.sorted,
-                     sv.off, (const float*)nullptr, (const BwdScalars*)nullptr, x.tw, (cf*)nullptr, v);
+  hipLaunchKernelGGL((k_splat_r2c<RES, MODE_VOUT>), dim3(3 * G::rows), dim3(G::BR), 0, x.stream, sv.sorted, sv.off,
+                     (const float*)nullptr, (const BwdScalars*)nullptr, x.tw, (cf*)nullptr, v);
   PSR_CHECK_LAUNCH();
   return 0;
 }

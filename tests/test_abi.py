@@ -42,7 +42,7 @@ def test_workspace_sizes(res):
     assert ws >= 2 * 3 * H * res * res * 8 + P * 32
     assert ws % 256 == 0
     sv = _lib.saved_bytes(res, P)
-    assert sv >= (res * res + 1) * 4 + P * 48
+    assert sv >= P * 48 + 256
 
 
 @pytest.mark.parametrize("res,P", [(0, 10), (7, 10), (1024, 10), (4, 10), (96, 10), (64, 0), (64, -5)])
