@@ -170,6 +170,103 @@ def make_step(b, ctx, backward: bool = True):
     return step
 
 
+def batch_c4(dev, torch, steps=10, warmup=3):
+    """64 shapes (res 64/128, P log-uniform 1e3..5e4, seed 3), fwd+bwd with
+    G = 2 chi / N (loss mean chi^2): one psr_run_batched call vs the same
+    solves as sequential psr_forward/psr_backward calls on one stream."""
+    if args.mode == "serve":
+        print(json.dumps(serve_mode(dev, torch, args.requests)), flush=True)
+        return
+
+    import psr_synth as S
+    from paper_2106_03452_amd import _lib
+    from paper_2106_03452_amd import function as F
+    from paper_2106_03452_amd.batch import BatchPlan, Job
+    shapes = S.config_c4()
+    jobs = []
+    for sh in shapes:
+        p = torch.from_numpy(sh.points).to(dev)
+        n = torch.from_numpy(sh.normals).to(dev)
+        chi, _ = F.forward(p, n, sh.res, sh.sigma)
+        jobs.append(Job(p, n, sh.res, sh.sigma, (2.0 * chi / chi.numel()).contiguous()))
+    plan = BatchPlan(jobs)
+    dt_b = timed(plan.run, steps, warmup, torch)
+    ctx = _lib.context(0)
+    steps_seq = []
+    for i, j in enumerate(jobs):
+        b = dict(pts=j.points, nrm=j.normals, chi=plan.chi[i], saved=plan.saved[i], G=j.dchi, ws=plan.ws[i],
+                 dp=plan.dp[i], dn=plan.dn[i], r=j.res, P=int(j.points.shape[0]), sigma=j.sigma)
+        steps_seq.append(make_step(b, ctx))
+
+    def seq():
+        for st in steps_seq:
+            st()
+    dt_s = timed(seq, steps, warmup, torch)
+    total_bytes = sum(b_stage(j.res, int(j.points.shape[0])) for j in jobs)
+    t_b = dt_b / steps
+    return {"workload": "64 shapes, res 64/128, P log-uniform [1e3, 5e4] (seed 3), fwd+bwd",
+            "shapes_per_s_batched": round(len(jobs) / t_b, 1),
+            "shapes_per_s_sequential": round(len(jobs) / (dt_s / steps), 1),
+            "ms_per_batch": round(t_b * 1e3, 4), "ms_sequential": round(dt_s / steps * 1e3, 4),
+            "step_roofline_frac": round(total_bytes / t_b / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def serve_mode(dev, torch, n_requests):
+    """Poisson request stream (seed 4): res in {64,128,256}, P log-uniform in
+    [3e3, 2e5], 50/50 forward vs forward+backward. lambda_seq = throughput of
+    sequential plain solves over the stream; then, at QPS = {0.5,0.8,1.0,1.5}
+    x lambda_seq, the continuous-batching engine and the sequential baseline
+    serve the same arrivals; p50/p99 latency skip the first 100 requests."""
+    import numpy as np
+    import psr_synth as S
+    from paper_2106_03452_amd import _lib
+    from paper_2106_03452_amd.serve import Engine, GpuBackend, Request, SequentialBaseline, drive, latency_stats
+    print(f"serve: generating {n_requests} requests", file=sys.stderr, flush=True)
+    reqs_spec, arrivals_unit = S.config_c5(n_requests=n_requests)
+    classes = {64: 200000, 128: 200000, 256: 200000}
+    data = []
+    rng = np.random.Generator(np.random.PCG64(44))
+    G = {r: torch.from_numpy((rng.standard_normal((r, r, r)) * 1e-6).astype(np.float32)).to(dev) for r in classes}
+    for sh, bwd in reqs_spec:
+        data.append((sh.res, sh.P, bwd, torch.from_numpy(sh.points).to(dev), torch.from_numpy(sh.normals).to(dev)))
+    torch.cuda.synchronize()
+
+    def make(arr):
+        return [Request(i, res, P, bwd, float(a), p, n, G[res] if bwd else None)
+                for i, ((res, P, bwd, p, n), a) in enumerate(zip(data, arr))]
+
+    seq = SequentialBaseline(0)
+    # warm up and measure lambda_seq: everything available at t = 0, one solve at a time
+    seq.run(make([0.0] * min(50, len(data))), classes)
+    rs = make([0.0] * len(data))
+    t0 = seq.run(rs, classes)
+    lam = len(rs) / (max(r.done for r in rs) - t0)
+    be = GpuBackend(0, num_streams=4)
+    budget = 48 << 30
+    warm = Engine(be, classes, budget)
+    drive(warm, make([0.0] * min(100, len(data))))
+    out = {"workload": f"{len(data)} requests, res 64/128/256, P log-uniform [3e3, 2e5], 50/50 fwd vs fwd+bwd, "
+                       "Poisson arrivals (seed 4)",
+           "lambda_seq_solves_per_s": round(lam, 1), "levels": []}
+    print(f"serve: lambda_seq = {lam:.1f} solves/s", file=sys.stderr, flush=True)
+    for f in (0.5, 0.8, 1.0, 1.5):
+        print(f"serve: level {f}", file=sys.stderr, flush=True)
+        qps = f * lam
+        arr = np.cumsum(arrivals_unit[:len(data)]) / qps
+        eng = Engine(be, classes, budget)
+        eng.classes = warm.classes  # resident slots carried over
+        eng.used = warm.used
+        r_e = make(arr)
+        t0e = drive(eng, r_e)
+        r_s = make(arr)
+        t0s = seq.run(r_s, classes)
+        thr = lambda rr, t0: len(rr) / (max(r.done for r in rr) - t0)
+        out["levels"].append({"qps_factor": f, "qps": round(qps, 1),
+                              "engine": {"solves_per_s": round(thr(r_e, t0e), 1), **latency_stats(r_e, 100)},
+                              "sequential": {"solves_per_s": round(thr(r_s, t0s), 1), **latency_stats(r_s, 100)}})
+    return out
+
+
 def timed(step, steps, warmup, torch):
     for _ in range(warmup):
         step()
@@ -188,6 +285,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the 128^3 and forward-only lines")
+    ap.add_argument("--mode", choices=["solve", "serve"], default="solve",
+                    help="solve: the fwd+bwd throughput line (default); serve: the request-stream measurement")
+    ap.add_argument("--requests", type=int, default=2000, help="serve mode: requests per QPS level")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -210,6 +310,10 @@ def main():
         dt = (time.perf_counter() - t0) / 5
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "ms": round(dt * 1e3, 4),
                           "GBs_read_plus_write": round(8 * n / dt / 1e9, 1)}), flush=True)
+        return
+
+    if args.mode == "serve":
+        print(json.dumps(serve_mode(dev, torch, args.requests)), flush=True)
         return
 
     import psr_synth as S
@@ -273,6 +377,7 @@ def main():
         secondary["fwd_only_128"] = {"solves_per_s": round(args.steps * 3 / d3, 2),
                                      "ms": round(d3 / (args.steps * 3) * 1e3, 4), "paper_gtx1080ti_ms": 12.0}
         del b2
+        secondary["batch_c4"] = batch_c4(dev, torch)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     out = {

@@ -108,11 +108,28 @@ bool valid_P(int64_t P) { return P >= 1 && P <= ((int64_t)1 << 30); }
 
 bool aligned(const void* p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
 
-psr::Exec make_exec(psr_ctx* ctx, float sigma, hipStream_t stream) {
+psr::JobArg make_job(const float* pts, const float* nrm, int64_t P, float sigma, float* chi, void* saved, void* ws) {
+  psr::JobArg j;
+  j.pts = pts;
+  j.nrm = nrm;
+  j.chi = chi;
+  j.dchi = nullptr;
+  j.dpts = nullptr;
+  j.dnrm = nullptr;
+  j.ws = ws;
+  j.sv = saved;
+  j.aux_in = nullptr;
+  j.aux_out = nullptr;
+  j.P = P;
+  j.sigma = sigma;
+  j.pad = 0;
+  return j;
+}
+
+psr::Exec make_exec(psr_ctx* ctx, hipStream_t stream) {
   psr::Exec x;
   x.stream = stream;
   x.tw = ctx->tw;
-  x.sigma = sigma;
   x.m = ctx->m;
   x.reading = ctx->reading;
   x.timers = ctx->timers;
@@ -246,12 +263,11 @@ int psr_forward(psr_ctx* ctx, const float* points, const float* normals, int64_t
   if (!ctx || !points || !normals || !chi || !saved || !workspace) return PSR_EINVAL;
   if (!valid_res(res) || !valid_P(npoints) || !(sigma >= 0.0f) || !std::isfinite(sigma)) return PSR_EINVAL;
   if (!aligned(saved, 256) || !aligned(workspace, 256) || !aligned(chi, 16)) return PSR_EINVAL;
-  const psr::WsLayout L = psr::ws_layout(res, npoints);
-  if (workspace_bytes < L.total) return PSR_EINVAL;
+  if (workspace_bytes < psr::ws_layout(res, npoints).total) return PSR_EINVAL;
   DeviceGuard g(ctx->device);
-  psr::Exec x = make_exec(ctx, sigma, stream);
-  return psr::run_forward(x, res, points, normals, npoints, chi, psr::ws_view(workspace, L),
-                          psr::saved_view(saved, psr::saved_layout(res, npoints)));
+  psr::Exec x = make_exec(ctx, stream);
+  psr::JobArg j = make_job(points, normals, npoints, sigma, chi, saved, workspace);
+  return psr::run_jobs(x, res, &j, 1, psr::RUN_FORWARD);
 }
 
 int psr_backward(psr_ctx* ctx, int64_t npoints, int res, float sigma, const float* chi, const void* saved,
@@ -261,12 +277,15 @@ int psr_backward(psr_ctx* ctx, int64_t npoints, int res, float sigma, const floa
   if (!valid_res(res) || !valid_P(npoints) || !(sigma >= 0.0f) || !std::isfinite(sigma)) return PSR_EINVAL;
   if (!aligned(saved, 256) || !aligned(workspace, 256) || !aligned(chi, 16) || !aligned(dchi, 16))
     return PSR_EINVAL;
-  const psr::WsLayout L = psr::ws_layout(res, npoints);
-  if (workspace_bytes < L.total) return PSR_EINVAL;
+  if (workspace_bytes < psr::ws_layout(res, npoints).total) return PSR_EINVAL;
   DeviceGuard g(ctx->device);
-  psr::Exec x = make_exec(ctx, sigma, stream);
-  return psr::run_backward(x, res, npoints, chi, dchi, dpoints, dnormals, psr::ws_view(workspace, L),
-                           psr::saved_view(const_cast<void*>(saved), psr::saved_layout(res, npoints)));
+  psr::Exec x = make_exec(ctx, stream);
+  psr::JobArg j = make_job(nullptr, nullptr, npoints, sigma, const_cast<float*>(chi), const_cast<void*>(saved),
+                           workspace);
+  j.dchi = dchi;
+  j.dpts = dpoints;
+  j.dnrm = dnormals;
+  return psr::run_jobs(x, res, &j, 1, psr::RUN_BACKWARD);
 }
 
 int psr_saved_status(const void* saved, hipStream_t stream, int* status) {
@@ -302,15 +321,31 @@ int psr_run_batched(psr_ctx* ctx, int njobs, const psr_job* jobs, hipStream_t st
     if (!aligned(j.saved, 256) || !aligned(j.workspace, 256) || !aligned(j.chi, 16)) return PSR_EINVAL;
     if (j.dchi && !aligned(j.dchi, 16)) return PSR_EINVAL;
   }
-  for (int i = 0; i < njobs; ++i) {
-    const psr_job& j = jobs[i];
-    int rc = psr_forward(ctx, j.points, j.normals, j.npoints, j.res, j.sigma, j.chi, j.saved, j.workspace,
-                         j.workspace_bytes, stream);
-    if (rc) return rc;
-    if (j.dchi) {
-      rc = psr_backward(ctx, j.npoints, j.res, j.sigma, j.chi, j.saved, j.dchi, j.dpoints, j.dnormals,
-                        j.workspace, j.workspace_bytes, stream);
-      if (rc) return rc;
+  DeviceGuard g(ctx->device);
+  psr::Exec x = make_exec(ctx, stream);
+  // group by resolution: one launch per stage and resolution (chunks of
+  // psr::kMaxJobs jobs); the forwards of every group, then the backwards
+  std::vector<psr::JobArg> fw, bw;
+  for (int res = PSR_MIN_RES; res <= PSR_MAX_RES; res *= 2) {
+    fw.clear();
+    bw.clear();
+    for (int i = 0; i < njobs; ++i) {
+      const psr_job& j = jobs[i];
+      if (j.res != res) continue;
+      psr::JobArg a = make_job(j.points, j.normals, j.npoints, j.sigma, j.chi, j.saved, j.workspace);
+      fw.push_back(a);
+      if (j.dchi) {
+        a.dchi = j.dchi;
+        a.dpts = j.dpoints;
+        a.dnrm = j.dnormals;
+        bw.push_back(a);
+      }
+    }
+    if (!fw.empty()) {
+      if (int rc = psr::run_jobs(x, res, fw.data(), (int)fw.size(), psr::RUN_FORWARD)) return rc;
+    }
+    if (!bw.empty()) {
+      if (int rc = psr::run_jobs(x, res, bw.data(), (int)bw.size(), psr::RUN_BACKWARD)) return rc;
     }
   }
   return PSR_OK;
@@ -321,11 +356,13 @@ int psr_debug_spectral(psr_ctx* ctx, const float* v, int res, float sigma, float
   if (!ctx || !v || !chi_prime || !workspace) return PSR_EINVAL;
   if (!valid_res(res) || !(sigma >= 0.0f) || !std::isfinite(sigma)) return PSR_EINVAL;
   if (!aligned(workspace, 256) || !aligned(v, 16)) return PSR_EINVAL;
-  const psr::WsLayout L = psr::ws_layout(res, 1);
-  if (workspace_bytes < L.total) return PSR_EINVAL;
+  if (workspace_bytes < psr::ws_layout(res, 1).total) return PSR_EINVAL;
   DeviceGuard g(ctx->device);
-  psr::Exec x = make_exec(ctx, sigma, stream);
-  return psr::run_debug_spectral(x, res, v, chi_prime, psr::ws_view(workspace, L));
+  psr::Exec x = make_exec(ctx, stream);
+  psr::JobArg j = make_job(nullptr, nullptr, 1, sigma, nullptr, nullptr, workspace);
+  j.aux_in = v;
+  j.aux_out = chi_prime;
+  return psr::run_debug_spectral(x, res, j);
 }
 
 int psr_debug_splat(psr_ctx* ctx, const float* points, const float* normals, int64_t npoints, int res, float* v,
@@ -333,12 +370,12 @@ int psr_debug_splat(psr_ctx* ctx, const float* points, const float* normals, int
   if (!ctx || !points || !normals || !v || !saved || !workspace) return PSR_EINVAL;
   if (!valid_res(res) || !valid_P(npoints)) return PSR_EINVAL;
   if (!aligned(saved, 256) || !aligned(workspace, 256)) return PSR_EINVAL;
-  const psr::WsLayout L = psr::ws_layout(res, npoints);
-  if (workspace_bytes < L.total) return PSR_EINVAL;
+  if (workspace_bytes < psr::ws_layout(res, npoints).total) return PSR_EINVAL;
   DeviceGuard g(ctx->device);
-  psr::Exec x = make_exec(ctx, 0.0f, stream);
-  return psr::run_debug_splat(x, res, points, normals, npoints, v, psr::ws_view(workspace, L),
-                              psr::saved_view(saved, psr::saved_layout(res, npoints)));
+  psr::Exec x = make_exec(ctx, stream);
+  psr::JobArg j = make_job(points, normals, npoints, 0.0f, nullptr, saved, workspace);
+  j.aux_out = v;
+  return psr::run_debug_splat(x, res, j);
 }
 
 int psr_ctx_stage_times(psr_ctx* ctx, double* ms, int64_t* counts, int n) {

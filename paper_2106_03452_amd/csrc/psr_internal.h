@@ -62,13 +62,13 @@ enum Stage {
 
 constexpr int kRedBlocks = 1024;  // fixed block count of the FP64 reductions (deterministic order)
 
-inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
   size_t bs, blockpart, X, Y, counts, tmp, colrank, part, total;
 };
 
-inline WsLayout ws_layout(int res, int64_t P) {
+__host__ __device__ inline WsLayout ws_layout(int res, int64_t P) {
   const size_t H = (size_t)res / 2 + 1;
   const size_t spec = 3 * H * (size_t)res * (size_t)res * 8;
   WsLayout L;
@@ -97,7 +97,7 @@ struct SavedLayout {
   size_t hdr, off, sorted, gradf, total;
 };
 
-inline SavedLayout saved_layout(int res, int64_t P) {
+__host__ __device__ inline SavedLayout saved_layout(int res, int64_t P) {
   SavedLayout L;
   size_t o = 0;
   L.hdr = o;
@@ -130,7 +130,7 @@ struct SavedView {
   float4* gradf;
 };
 
-inline WsView ws_view(void* base, const WsLayout& L) {
+__host__ __device__ inline WsView ws_view(void* base, const WsLayout& L) {
   char* b = static_cast<char*>(base);
   WsView w;
   w.X = reinterpret_cast<cf*>(b + L.X);
@@ -144,7 +144,7 @@ inline WsView ws_view(void* base, const WsLayout& L) {
   return w;
 }
 
-inline SavedView saved_view(void* base, const SavedLayout& L) {
+__host__ __device__ inline SavedView saved_view(void* base, const SavedLayout& L) {
   char* b = static_cast<char*>(base);
   SavedView s;
   s.hdr = reinterpret_cast<SavedHeader*>(b + L.hdr);
@@ -154,6 +154,37 @@ inline SavedView saved_view(void* base, const SavedLayout& L) {
   return s;
 }
 
+// One solve as the kernels see it (passed by value inside a Batch).
+struct JobArg {
+  const float* pts;
+  const float* nrm;
+  float* chi;
+  const float* dchi;
+  float* dpts;
+  float* dnrm;
+  void* ws;
+  void* sv;
+  const float* aux_in;  // test hooks: field v in
+  float* aux_out;       // test hooks: field v out
+  int64_t P;
+  float sigma;
+  int pad;
+};
+
+// Up to MAXJ solves of one resolution in one launch: workgroups
+// [start[j], start[j+1]) belong to job j.
+template <int MAXJ>
+struct Batch {
+  const cf* tw;
+  float m;
+  int reading;
+  int n;
+  int start[MAXJ + 1];
+  JobArg job[MAXJ];
+};
+
+constexpr int kMaxJobs = 24;  // jobs per batched launch (kernel argument stays under 4 KiB)
+
 struct Timers;
 void timer_begin(Timers* t, int stage, hipStream_t s);
 void timer_end(Timers* t, int stage, hipStream_t s);
@@ -162,7 +193,6 @@ void timer_end(Timers* t, int stage, hipStream_t s);
 struct Exec {
   hipStream_t stream;
   const cf* tw;  // twiddle tables: table of length L at offset L
-  float sigma;
   double m;
   int reading;
   Timers* timers;  // null when timing is off
@@ -174,12 +204,11 @@ struct Exec {
   }
 };
 
-int run_forward(Exec& x, int res, const float* pts, const float* nrm, int64_t P, float* chi, const WsView& w,
-                const SavedView& sv);
-int run_backward(Exec& x, int res, int64_t P, const float* chi, const float* dchi, float* dpts, float* dnrm,
-                 const WsView& w, const SavedView& sv);
-int run_debug_spectral(Exec& x, int res, const float* v, float* chi_prime, const WsView& w);
-int run_debug_splat(Exec& x, int res, const float* pts, const float* nrm, int64_t P, float* v, const WsView& w,
-                    const SavedView& sv);
+enum RunWhat { RUN_FORWARD = 1, RUN_BACKWARD = 2 };
+
+// Run forward and/or backward for n jobs of one resolution.
+int run_jobs(Exec& x, int res, const JobArg* jobs, int n, int what);
+int run_debug_spectral(Exec& x, int res, const JobArg& job);
+int run_debug_splat(Exec& x, int res, const JobArg& job);
 
 }  // namespace psr

@@ -47,34 +47,55 @@ __device__ __forceinline__ void load_rec(const PointRec* __restrict__ s, int64_t
 // Point ranges (in sorted order) whose 2x2 corner lines can touch the row
 // tile (j0, j1 in [tb*TR, tb*TR + TR)): bins of floor rows b0 in {j0-1, j0}
 // and of row tiles tb-1 and tb (the last column of tile tb-1 reaches line
-// tb*TR through its +1 corner). Up to 4 disjoint ranges.
+// tb*TR through its +1 corner). Four disjoint ranges, unused ones empty;
+// kept in named scalars so nothing is indexed dynamically.
+struct Ranges {
+  int lo[4], n[4];
+  int total;
+};
+
 template <int RES>
-__device__ __forceinline__ int tile_ranges(const int* __restrict__ off, int j0, int tb, int* lo, int* hi) {
+__device__ __forceinline__ Ranges tile_ranges(const int* __restrict__ off, int j0, int tb) {
   constexpr int NT = row_tiles(RES);
-  int nr = 0;
+  Ranges R;
 #pragma unroll
   for (int o = 0; o < 2; ++o) {
     const int rb = ((j0 - 1 + o) & (RES - 1)) * NT;
+    int a, b, c, d;
     if constexpr (NT == 1) {
-      lo[nr] = off[rb];
-      hi[nr] = off[rb + 1];
-      ++nr;
+      a = off[rb];
+      b = off[rb + 1];
+      c = 0;
+      d = 0;
     } else {
       if (tb > 0) {
-        lo[nr] = off[rb + tb - 1];
-        hi[nr] = off[rb + tb + 1];
-        ++nr;
+        a = off[rb + tb - 1];
+        b = off[rb + tb + 1];
+        c = 0;
+        d = 0;
       } else {
-        lo[nr] = off[rb + NT - 1];
-        hi[nr] = off[rb + NT];
-        ++nr;
-        lo[nr] = off[rb];
-        hi[nr] = off[rb + 1];
-        ++nr;
+        a = off[rb + NT - 1];
+        b = off[rb + NT];
+        c = off[rb];
+        d = off[rb + 1];
       }
     }
+    R.lo[2 * o] = a;
+    R.n[2 * o] = b - a;
+    R.lo[2 * o + 1] = c;
+    R.n[2 * o + 1] = d - c;
   }
-  return nr;
+  R.total = R.n[0] + R.n[1] + R.n[2] + R.n[3];
+  return R;
+}
+
+// Sorted index of the q-th point of the ranges (q < R.total).
+__device__ __forceinline__ int64_t range_pick(const Ranges& R, int q) {
+  int64_t s = R.lo[3] + (q - R.n[0] - R.n[1] - R.n[2]);
+  if (q < R.n[0] + R.n[1] + R.n[2]) s = R.lo[2] + (q - R.n[0] - R.n[1]);
+  if (q < R.n[0] + R.n[1]) s = R.lo[1] + (q - R.n[0]);
+  if (q < R.n[0]) s = R.lo[0] + q;
+  return s;
 }
 
 // Copy the twiddle table of length L (exp(-2 pi i e / L), e in [0, n)) into
@@ -85,22 +106,14 @@ __device__ __forceinline__ void stage_table(cf* dst, const cf* __restrict__ src,
   for (int e = threadIdx.x; e < n; e += BLOCK) dst[e] = src[e];
 }
 
-__device__ __forceinline__ int64_t range_pick(const int* lo, const int* hi, int nr, int q) {
-  for (int r = 0; r < nr; ++r) {
-    const int n = hi[r] - lo[r];
-    if (q < n) return lo[r] + q;
-    q -= n;
-  }
-  return -1;
-}
 
 // ---------------------------------------------------------------------------
 // binning: counting sort of the points by row tile (b0, b1 / tile_rows)
 // ---------------------------------------------------------------------------
-__global__ void k_init(int* __restrict__ counts, int n, SavedHeader* __restrict__ hdr, int res,
-                       int64_t npoints, float sigma, float m, int reading) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) counts[i] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+__device__ __forceinline__ void b_init(int* __restrict__ counts, int n, SavedHeader* __restrict__ hdr, int res,
+                       int64_t npoints, float sigma, float m, int reading, int bid, int nblocks) {
+  for (int i = bid * blockDim.x + threadIdx.x; i < n; i += nblocks * blockDim.x) counts[i] = 0;
+  if (bid == 0 && threadIdx.x == 0) {
     hdr->status = 0;
     hdr->flags = 0;
     hdr->res = res;
@@ -118,10 +131,10 @@ __global__ void k_init(int* __restrict__ counts, int n, SavedHeader* __restrict_
 constexpr int kBinChunk = 1024;
 
 template <int RES>
-__global__ __launch_bounds__(256) void k_bin(const float* __restrict__ pts, const float* __restrict__ nrm,
+__device__ __forceinline__ void b_bin(const float* __restrict__ pts, const float* __restrict__ nrm,
                                              int64_t npoints, int* __restrict__ counts,
                                              PointRec* __restrict__ tmp, int2* __restrict__ colrank,
-                                             SavedHeader* __restrict__ hdr) {
+                                             SavedHeader* __restrict__ hdr, int bid) {
   constexpr int NB = num_bins(RES);
   constexpr int PPT = kBinChunk / 256;
   __shared__ int hist[NB];
@@ -132,7 +145,7 @@ __global__ __launch_bounds__(256) void k_bin(const float* __restrict__ pts, cons
   bool anybad = false;
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
-    const int64_t i = (int64_t)blockIdx.x * kBinChunk + u * 256 + t;
+    const int64_t i = (int64_t)bid * kBinChunk + u * 256 + t;
     mybin[u] = -1;
     if (i >= npoints) continue;
     float f[3], n[3];
@@ -182,14 +195,14 @@ __global__ __launch_bounds__(256) void k_bin(const float* __restrict__ pts, cons
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
-    const int64_t i = (int64_t)blockIdx.x * kBinChunk + u * 256 + t;
+    const int64_t i = (int64_t)bid * kBinChunk + u * 256 + t;
     if (mybin[u] >= 0) colrank[i] = make_int2(mybin[u], hist[mybin[u]] + myrank[u]);
   }
 }
 
 // Exclusive scan of n counts into off[0..n]: one workgroup of 1024 threads,
 // coalesced rounds of 1024 elements, wavefront shuffles + a carry.
-__global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ counts, int* __restrict__ off, int n) {
+__device__ __forceinline__ void b_scan(const int* __restrict__ counts, int* __restrict__ off, int n, int bid) {
   __shared__ int wsum[16];
   const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
   int carry = 0;
@@ -222,9 +235,9 @@ __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ counts, i
   if (t == 0) off[n] = carry;
 }
 
-__global__ void k_scatter(const PointRec* __restrict__ tmp, const int2* __restrict__ colrank,
-                          const int* __restrict__ off, PointRec* __restrict__ sorted, int64_t npoints) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void b_scatter(const PointRec* __restrict__ tmp, const int2* __restrict__ colrank,
+                          const int* __restrict__ off, PointRec* __restrict__ sorted, int64_t npoints, int bid) {
+  const int64_t i = (int64_t)bid * blockDim.x + threadIdx.x;
   if (i >= npoints) return;
   const int2 cr = colrank[i];
   sorted[off[cr.x] + cr.y] = tmp[i];
@@ -240,12 +253,12 @@ __global__ void k_scatter(const PointRec* __restrict__ tmp, const int2* __restri
 enum { MODE_SPLAT = 0, MODE_BWDH = 1, MODE_LOADV = 2, MODE_VOUT = 3 };
 
 template <int RES, int MODE>
-__global__ __launch_bounds__(rows_block(RES)) void k_splat_r2c(const PointRec* __restrict__ sorted,
+__device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
                                                               const int* __restrict__ off,
                                                               const float* __restrict__ gin,
                                                               const BwdScalars* __restrict__ bs,
                                                               const cf* __restrict__ tw, cf* __restrict__ out,
-                                                              float* __restrict__ vout) {
+                                                              float* __restrict__ vout, int bid) {
   constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_block(RES);
   constexpr int TPL = plan_TPL(M), E = plan_E(M), LS = lstride(M);
   constexpr int64_t N3 = (int64_t)RES * RES * RES;
@@ -257,18 +270,16 @@ __global__ __launch_bounds__(rows_block(RES)) void k_splat_r2c(const PointRec* _
     stage_table<BR>(rtw, tw + RES, M + 1);
   }
   float* rf = reinterpret_cast<float*>(rows);
-  int b = blockIdx.x;
+  int b = bid;
   const int tb = b % NT;
   b /= NT;
   const int j0 = b % RES;
   const int c = b / RES;
   const int a0 = tb * TR;
   const int t = threadIdx.x;
-  int lo[4], hi[4], nr = 0, total = 0;
-  if constexpr (MODE != MODE_LOADV) {
-    nr = tile_ranges<RES>(off, j0, tb, lo, hi);
-    for (int r = 0; r < nr; ++r) total += hi[r] - lo[r];
-  }
+  Ranges R{};
+  if constexpr (MODE != MODE_LOADV) R = tile_ranges<RES>(off, j0, tb);
+  const int total = R.total;
   if constexpr (MODE == MODE_SPLAT) {
     // no point touches this tile: its rows and their spectra are zero
     if (total == 0) {
@@ -318,7 +329,7 @@ __global__ __launch_bounds__(rows_block(RES)) void k_splat_r2c(const PointRec* _
     if constexpr (MODE == MODE_BWDH) alpha = bs->alpha;
     __syncthreads();
     for (int qd = t; qd < total; qd += BR) {
-      const int64_t s = range_pick(lo, hi, nr, qd);
+      const int64_t s = range_pick(R, qd);
       float4 p0, p1;
       load_rec(sorted, s, p0, p1);
       const uint32_t bb = __float_as_uint(p0.w);
@@ -409,14 +420,14 @@ __device__ __forceinline__ void store_transposed(cf* rows, const cf* reg, cf* __
 //   channels 1 and 2 because their operator factors do not vary along j0.
 // ---------------------------------------------------------------------------
 template <int RES, bool MERGE>
-__global__ __launch_bounds__(cols_block(RES)) void k_axis1_fwd(const cf* __restrict__ in, cf* __restrict__ out,
-                                                               const cf* __restrict__ tw) {
+__device__ __forceinline__ void b_axis1_fwd(const cf* __restrict__ in, cf* __restrict__ out,
+                                                               const cf* __restrict__ tw, int bid) {
   constexpr int H = RES / 2 + 1, TC = tile_cols(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
   constexpr int64_t CH = (int64_t)H * RES * RES;  // elements per channel
   __shared__ cf rows[TC * LS];
   __shared__ cf stw[RES];
   stage_table<cols_block(RES)>(stw, tw + RES, RES);
-  int b = blockIdx.x;
+  int b = bid;
   const int tb = b % (RES / TC);
   b /= RES / TC;
   const int k2 = b % H;
@@ -477,16 +488,16 @@ __device__ __forceinline__ float spectral_F(const float* g1, int k0, float g12, 
 }
 
 template <int RES>
-__global__ __launch_bounds__(cols_block(RES)) void k_fwd_axis0(const cf* __restrict__ in, cf* __restrict__ out,
-                                                               const cf* __restrict__ tw, float sigma) {
+__device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __restrict__ out,
+                                                               const cf* __restrict__ tw, float sigma, int bid) {
   constexpr int H = RES / 2 + 1, TC = tile_cols(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
   __shared__ cf rows[TC * LS];
   __shared__ cf stw[RES];
   __shared__ float g1[RES];
   stage_table<cols_block(RES)>(stw, tw + RES, RES);
   gauss_table<RES, cols_block(RES)>(g1, sigma);
-  const int tb = blockIdx.x % (RES / TC);
-  const int k2 = blockIdx.x / (RES / TC);
+  const int tb = bid % (RES / TC);
+  const int k2 = bid / (RES / TC);
   const int a0 = tb * TC;
   const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
   const int k1 = a0 + l;
@@ -523,16 +534,16 @@ __global__ __launch_bounds__(cols_block(RES)) void k_fwd_axis0(const cf* __restr
 // unscaled channel U = IFFT_k0(-i F H^) serves both (kappa_1 is applied in
 // the k1 pass, kappa_2 in the k2 pass). B[k1][k2][j0] -> C[2][j0][k2][k1].
 template <int RES>
-__global__ __launch_bounds__(cols_block(RES)) void k_bwd_axis0(const cf* __restrict__ in, cf* __restrict__ out,
-                                                               const cf* __restrict__ tw, float sigma) {
+__device__ __forceinline__ void b_bwd_axis0(const cf* __restrict__ in, cf* __restrict__ out,
+                                                               const cf* __restrict__ tw, float sigma, int bid) {
   constexpr int H = RES / 2 + 1, TC = tile_cols(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
   __shared__ cf rows[TC * LS];
   __shared__ cf stw[RES];
   __shared__ float g1[RES];
   stage_table<cols_block(RES)>(stw, tw + RES, RES);
   gauss_table<RES, cols_block(RES)>(g1, sigma);
-  const int tb = blockIdx.x % (RES / TC);
-  const int k2 = blockIdx.x / (RES / TC);
+  const int tb = bid % (RES / TC);
+  const int k2 = bid / (RES / TC);
   const int a0 = tb * TC;
   const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
   const int k1 = a0 + l;
@@ -565,14 +576,14 @@ __global__ __launch_bounds__(cols_block(RES)) void k_bwd_axis0(const cf* __restr
 //   the c2r pass applies).
 // ---------------------------------------------------------------------------
 template <int RES, bool SPLIT>
-__global__ __launch_bounds__(cols_block(RES)) void k_axis1_inv(const cf* __restrict__ in, cf* __restrict__ out,
-                                                               const cf* __restrict__ tw) {
+__device__ __forceinline__ void b_axis1_inv(const cf* __restrict__ in, cf* __restrict__ out,
+                                                               const cf* __restrict__ tw, int bid) {
   constexpr int H = RES / 2 + 1, TC = tile_cols(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
   constexpr int64_t CH = (int64_t)H * RES * RES;
   __shared__ cf rows[TC * LS];
   __shared__ cf stw[RES];
   stage_table<cols_block(RES)>(stw, tw + RES, RES);
-  int b = blockIdx.x;
+  int b = bid;
   const int tb = b % (RES / TC);
   b /= RES / TC;
   const int k2 = b % H;
@@ -617,12 +628,12 @@ __global__ __launch_bounds__(cols_block(RES)) void k_axis1_inv(const cf* __restr
 enum { MODE_FWD = 0, MODE_BWD = 1, MODE_DBG = 2 };
 
 template <int RES, int MODE>
-__global__ __launch_bounds__(rows_block(RES)) void k_c2r_gather(const cf* __restrict__ in,
+__device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
                                                                float* __restrict__ chi_out,
                                                                const PointRec* __restrict__ sorted,
                                                                const int* __restrict__ off,
                                                                float4* __restrict__ part,
-                                                               const cf* __restrict__ tw) {
+                                                               const cf* __restrict__ tw, int bid) {
   constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_block(RES);
   constexpr int TPL = plan_TPL(M), E = plan_E(M), LS = lstride(M);
   __shared__ cf rows[TR * LS];
@@ -631,17 +642,17 @@ __global__ __launch_bounds__(rows_block(RES)) void k_c2r_gather(const cf* __rest
   stage_table<BR>(stw, tw + M, M);
   stage_table<BR>(rtw, tw + RES, M + 1);
   const float* rf = reinterpret_cast<const float*>(rows);
-  int b = blockIdx.x;
+  int b = bid;
   const int tb = b % NT;
   b /= NT;
   const int j0 = b % RES;
   const int c = b / RES;
   const int a0 = tb * TR;
   const int t = threadIdx.x;
-  int lo[4], hi[4], nr = 0, total = 0;
+  Ranges R{};
+  if constexpr (MODE != MODE_DBG) R = tile_ranges<RES>(off, j0, tb);
+  const int total = R.total;
   if constexpr (MODE != MODE_DBG) {
-    nr = tile_ranges<RES>(off, j0, tb, lo, hi);
-    for (int r = 0; r < nr; ++r) total += hi[r] - lo[r];
     // the backward pass only produces per-point partials: a tile that no
     // point touches has nothing to do (uniform across the workgroup)
     if (MODE == MODE_BWD && total == 0) return;
@@ -718,7 +729,7 @@ __global__ __launch_bounds__(rows_block(RES)) void k_c2r_gather(const cf* __rest
   }
   if constexpr (MODE != MODE_DBG) {
     for (int qd = t; qd < total; qd += BR) {
-      const int64_t s = range_pick(lo, hi, nr, qd);
+      const int64_t s = range_pick(R, qd);
       float4 p0, p1;
       load_rec(sorted, s, p0, p1);
       const uint32_t bb = __float_as_uint(p0.w);
@@ -769,11 +780,11 @@ __device__ __forceinline__ Tv block_sum(Tv v, Tv* sh) {
 }
 
 // Per point: f_i = sum of its 4 corner-line partials (FP64), grad f_i (FP32).
-__global__ __launch_bounds__(256) void k_fwd_point_reduce(const float4* __restrict__ part, int64_t npoints,
-                                                          float4* __restrict__ gradf, double* __restrict__ blockpart) {
+__device__ __forceinline__ void b_fwd_point_reduce(const float4* __restrict__ part, int64_t npoints,
+                                                          float4* __restrict__ gradf, double* __restrict__ blockpart, int bid, int nblocks) {
   __shared__ double sh[256];
   double acc = 0.0;
-  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < npoints; s += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t s = (int64_t)bid * blockDim.x + threadIdx.x; s < npoints; s += (int64_t)nblocks * blockDim.x) {
     const float4 q0 = part[s * 4 + 0], q1 = part[s * 4 + 1], q2 = part[s * 4 + 2], q3 = part[s * 4 + 3];
     const double f = ((double)q0.x + (double)q1.x) + ((double)q2.x + (double)q3.x);
     gradf[s] = make_float4((q0.y + q1.y) + (q2.y + q3.y), (q0.z + q1.z) + (q2.z + q3.z),
@@ -781,13 +792,13 @@ __global__ __launch_bounds__(256) void k_fwd_point_reduce(const float4* __restri
     acc += f;
   }
   const double tot = block_sum(acc, sh);
-  if (threadIdx.x == 0) blockpart[blockIdx.x] = tot;
+  if (threadIdx.x == 0) blockpart[bid] = tot;
 }
 
 // mu = (1/P) sum_i f_i, c = chi'(0) - mu (reading B) or chi'(0) (reading A),
 // s = m/|c| (main Eq. 4), status; block partials summed in a fixed order.
-__global__ __launch_bounds__(256) void k_fwd_scalars(const double* __restrict__ blockpart, int nb,
-                                                     const float* __restrict__ chi, SavedHeader* __restrict__ hdr) {
+__device__ __forceinline__ void b_fwd_scalars(const double* __restrict__ blockpart, int nb,
+                                                     const float* __restrict__ chi, SavedHeader* __restrict__ hdr, int bid) {
   __shared__ double sh[256];
   double a = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) a += blockpart[i];
@@ -807,10 +818,10 @@ __global__ __launch_bounds__(256) void k_fwd_scalars(const double* __restrict__ 
   }
 }
 
-__global__ void k_normalize(float* __restrict__ chi, int64_t n, const SavedHeader* __restrict__ hdr) {
+__device__ __forceinline__ void b_normalize(float* __restrict__ chi, int64_t n, const SavedHeader* __restrict__ hdr, int bid, int nblocks) {
   const double mu = hdr->mu, s = hdr->scale;
   float4* c4 = reinterpret_cast<float4*>(chi);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n / 4; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n / 4; i += (int64_t)nblocks * blockDim.x) {
     float4 v = c4[i];
     v.x = (float)(((double)v.x - mu) * s);
     v.y = (float)(((double)v.y - mu) * s);
@@ -821,25 +832,25 @@ __global__ void k_normalize(float* __restrict__ chi, int64_t n, const SavedHeade
 }
 
 // Backward: S_G = sum G, S_Gchi = sum G chi (FP64 partials per block).
-__global__ __launch_bounds__(256) void k_bwd_reduce(const float* __restrict__ G, const float* __restrict__ chi,
-                                                    int64_t n, double2* __restrict__ blockpart) {
+__device__ __forceinline__ void b_bwd_reduce(const float* __restrict__ G, const float* __restrict__ chi,
+                                                    int64_t n, double2* __restrict__ blockpart, int bid, int nblocks) {
   __shared__ double sh[256];
   double sg = 0.0, sgc = 0.0;
   const float4* g4 = reinterpret_cast<const float4*>(G);
   const float4* c4 = reinterpret_cast<const float4*>(chi);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n / 4; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n / 4; i += (int64_t)nblocks * blockDim.x) {
     const float4 g = g4[i], c = c4[i];
     sg += ((double)g.x + (double)g.y) + ((double)g.z + (double)g.w);
     sgc += ((double)g.x * c.x + (double)g.y * c.y) + ((double)g.z * c.z + (double)g.w * c.w);
   }
   const double a = block_sum(sg, sh);
   const double b = block_sum(sgc, sh);
-  if (threadIdx.x == 0) blockpart[blockIdx.x] = make_double2(a, b);
+  if (threadIdx.x == 0) blockpart[bid] = make_double2(a, b);
 }
 
 // Q = S_Gchi / c, g_mu = -s S_G + Q (reading B; reading A drops Q), alpha = g_mu / P.
-__global__ __launch_bounds__(256) void k_bwd_scalars(const double2* __restrict__ blockpart, int nb,
-                                                     const SavedHeader* __restrict__ hdr, BwdScalars* __restrict__ bs) {
+__device__ __forceinline__ void b_bwd_scalars(const double2* __restrict__ blockpart, int nb,
+                                                     const SavedHeader* __restrict__ hdr, BwdScalars* __restrict__ bs, int bid) {
   __shared__ double sh[256];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) {
@@ -862,10 +873,10 @@ __global__ __launch_bounds__(256) void k_bwd_scalars(const double2* __restrict__
   }
 }
 
-__global__ void k_bwd_point_finalize(const float4* __restrict__ part, const float4* __restrict__ gradf,
+__device__ __forceinline__ void b_bwd_point_finalize(const float4* __restrict__ part, const float4* __restrict__ gradf,
                                      const PointRec* __restrict__ sorted, const BwdScalars* __restrict__ bs,
-                                     int64_t npoints, float* __restrict__ dpoints, float* __restrict__ dnormals) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                     int64_t npoints, float* __restrict__ dpoints, float* __restrict__ dnormals, int bid) {
+  const int64_t s = (int64_t)bid * blockDim.x + threadIdx.x;
   if (s >= npoints) return;
   float4 p0, p1;
   load_rec(sorted, s, p0, p1);
@@ -905,134 +916,283 @@ __global__ void k_bwd_point_finalize(const float4* __restrict__ part, const floa
 }
 
 // ---------------------------------------------------------------------------
-// host-side launchers, one instantiation per resolution
+// __global__ wrappers: resolve the job of this workgroup and its buffers.
 // ---------------------------------------------------------------------------
-#define PSR_CHECK_LAUNCH()                          \
-  do {                                              \
-    if (hipGetLastError() != hipSuccess) return -4; \
-  } while (0)
+template <int MAXJ>
+__device__ __forceinline__ int job_of(const Batch<MAXJ>& B, int blk) {
+  if constexpr (MAXJ == 1) {
+    return 0;
+  } else {
+    int lo = 0, hi = B.n - 1;  // last j with start[j] <= blk
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (B.start[mid] <= blk) lo = mid;
+      else hi = mid - 1;
+    }
+    return lo;
+  }
+}
 
+#define PSR_JOB(RES)                                                  \
+  const int j_ = job_of(B, blockIdx.x);                               \
+  const int bid = blockIdx.x - B.start[j_];                           \
+  const int nbl = B.start[j_ + 1] - B.start[j_];                      \
+  const JobArg& J = B.job[j_];                                        \
+  const WsView w = ws_view(J.ws, ws_layout(RES, J.P));                \
+  const SavedView sv = saved_view(J.sv, saved_layout(RES, J.P));      \
+  (void)nbl;                                                          \
+  (void)w;                                                            \
+  (void)sv
+
+template <int RES, int MAXJ>
+__global__ __launch_bounds__(256) void k_init(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  b_init(w.counts, num_bins(RES), sv.hdr, RES, J.P, J.sigma, B.m, B.reading, bid, nbl);
+}
+
+template <int RES, int MAXJ>
+__global__ __launch_bounds__(256) void k_bin(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  b_bin<RES>(J.pts, J.nrm, J.P, w.counts, w.tmp, w.colrank, sv.hdr, bid);
+}
+
+template <int RES, int MAXJ>
+__global__ __launch_bounds__(1024) void k_scan(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  b_scan(w.counts, sv.off, num_bins(RES), bid);
+}
+
+template <int RES, int MAXJ>
+__global__ __launch_bounds__(256) void k_scatter(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  b_scatter(w.tmp, w.colrank, sv.off, sv.sorted, J.P, bid);
+}
+
+template <int RES, int MODE, int MAXJ>
+__global__ __launch_bounds__(rows_block(RES)) void k_splat_r2c(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  const float* gin = MODE == MODE_BWDH ? J.dchi : J.aux_in;
+  b_splat_r2c<RES, MODE>(sv.sorted, sv.off, gin, w.bs, B.tw, w.X, J.aux_out, bid);
+}
+
+template <int RES, bool MERGE, int MAXJ>
+__global__ __launch_bounds__(cols_block(RES)) void k_axis1_fwd(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  b_axis1_fwd<RES, MERGE>(w.X, w.Y, B.tw, bid);
+}
+
+template <int RES, int MAXJ>
+__global__ __launch_bounds__(cols_block(RES)) void k_fwd_axis0(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  b_fwd_axis0<RES>(w.Y, w.X, B.tw, J.sigma, bid);
+}
+
+template <int RES, int MAXJ>
+__global__ __launch_bounds__(cols_block(RES)) void k_bwd_axis0(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  b_bwd_axis0<RES>(w.Y, w.X, B.tw, J.sigma, bid);
+}
+
+template <int RES, bool SPLIT, int MAXJ>
+__global__ __launch_bounds__(cols_block(RES)) void k_axis1_inv(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  b_axis1_inv<RES, SPLIT>(w.X, w.Y, B.tw, bid);
+}
+
+template <int RES, int MODE, int MAXJ>
+__global__ __launch_bounds__(rows_block(RES)) void k_c2r_gather(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  float* out = MODE == MODE_DBG ? J.aux_out : J.chi;
+  b_c2r_gather<RES, MODE>(w.Y, out, sv.sorted, sv.off, w.part, B.tw, bid);
+}
+
+template <int RES, int MAXJ>
+__global__ __launch_bounds__(256) void k_fwd_point_reduce(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  b_fwd_point_reduce(w.part, J.P, sv.gradf, w.blockpart, bid, nbl);
+}
+
+template <int RES, int MAXJ>
+__global__ __launch_bounds__(256) void k_fwd_scalars(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  const int nb = (int)((J.P + 255) / 256) > kRedBlocks ? kRedBlocks : (int)((J.P + 255) / 256);
+  b_fwd_scalars(w.blockpart, nb, J.chi, sv.hdr, bid);
+}
+
+template <int RES, int MAXJ>
+__global__ __launch_bounds__(256) void k_normalize(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  b_normalize(J.chi, (int64_t)RES * RES * RES, sv.hdr, bid, nbl);
+}
+
+template <int RES, int MAXJ>
+__global__ __launch_bounds__(256) void k_bwd_reduce(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  b_bwd_reduce(J.dchi, J.chi, (int64_t)RES * RES * RES, (double2*)w.blockpart, bid, nbl);
+}
+
+// blocks of the grid-stride FP64 reduction over RES^3 / 4 float4 (at least 1)
+template <int RES>
+constexpr int bwd_reduce_blocks() {
+  constexpr int64_t n = ((int64_t)RES * RES * RES / 4 + 255) / 256;
+  return n > kRedBlocks ? kRedBlocks : (int)n;
+}
+
+template <int RES, int MAXJ>
+__global__ __launch_bounds__(256) void k_bwd_scalars(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  b_bwd_scalars((const double2*)w.blockpart, bwd_reduce_blocks<RES>(), sv.hdr, w.bs, bid);
+}
+
+template <int RES, int MAXJ>
+__global__ __launch_bounds__(256) void k_bwd_point_finalize(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  b_bwd_point_finalize(w.part, sv.gradf, sv.sorted, w.bs, J.P, J.dpts, J.dnrm, bid);
+}
+
+// ---------------------------------------------------------------------------
+// host-side launch sequences
+// ---------------------------------------------------------------------------
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
+constexpr int nblk_c(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 template <int RES>
 struct Grid {
   static constexpr int H = RES / 2 + 1;
-  static constexpr int rows = RES * row_tiles(RES);      // row-pass workgroups per channel
+  static constexpr int rows = RES * row_tiles(RES);        // row-pass workgroups per channel
   static constexpr int cols = H * (RES / tile_cols(RES));  // column-pass workgroups per channel
   static constexpr int BR = rows_block(RES), BC = cols_block(RES);
+  static constexpr int64_t N3 = (int64_t)RES * RES * RES;
+  static constexpr int init_blocks = nblk_c(num_bins(RES), 256) > 64 ? 64 : nblk_c(num_bins(RES), 256);
+  static constexpr int norm_blocks = nblk_c(N3 / 4, 256) > 4096 ? 4096 : nblk_c(N3 / 4, 256);
 };
 
-template <int RES>
-static int launch_bin(Exec& x, const float* pts, const float* nrm, int64_t P, const WsView& w, const SavedView& sv) {
-  constexpr int NB = num_bins(RES);
-  x.begin(STAGE_BIN);
-  hipLaunchKernelGGL(k_init, dim3(nblk(NB, 256) > 64 ? 64 : nblk(NB, 256)), dim3(256), 0, x.stream, w.counts, NB,
-                     sv.hdr, RES, P, x.sigma, (float)x.m, x.reading);
-  hipLaunchKernelGGL(k_bin<RES>, dim3(nblk(P, kBinChunk)), dim3(256), 0, x.stream, pts, nrm, P, w.counts, w.tmp,
-                     w.colrank, sv.hdr);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, x.stream, w.counts, sv.off, NB);
-  hipLaunchKernelGGL(k_scatter, dim3(nblk(P, 256)), dim3(256), 0, x.stream, w.tmp, w.colrank, sv.off, sv.sorted, P);
-  x.end(STAGE_BIN);
-  PSR_CHECK_LAUNCH();
-  return 0;
+// Launch kernel K once per chunk of up to MAXJ jobs; workgroups per job from nb(job).
+template <int MAXJ, typename NB>
+static int launch(Exec& x, void (*K)(const Batch<MAXJ>), int block, const JobArg* jobs, int n, NB nb) {
+  for (int c0 = 0; c0 < n; c0 += MAXJ) {
+    Batch<MAXJ> B;
+    B.tw = x.tw;
+    B.m = (float)x.m;
+    B.reading = x.reading;
+    B.n = n - c0 < MAXJ ? n - c0 : MAXJ;
+    int total = 0;
+    for (int j = 0; j < B.n; ++j) {
+      B.job[j] = jobs[c0 + j];
+      B.start[j] = total;
+      const int nbj = nb(jobs[c0 + j]);
+      if (nbj < 1) return -4;  // every stage has work for every job
+      total += nbj;
+    }
+    B.start[B.n] = total;
+    hipLaunchKernelGGL(K, dim3(total), dim3(block), 0, x.stream, B);
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
-template <int RES>
-static int launch_forward(Exec& x, const float* pts, const float* nrm, int64_t P, float* chi, const WsView& w,
-                          const SavedView& sv) {
+template <int RES, int MAXJ>
+static int seq_forward(Exec& x, const JobArg* J, int n) {
   using G = Grid<RES>;
-  constexpr int64_t N3 = (int64_t)RES * RES * RES;
-  if (int rc = launch_bin<RES>(x, pts, nrm, P, w, sv)) return rc;
+  int rc = 0;
+  auto c = [](int v) { return [v](const JobArg&) { return v; }; };
+  x.begin(STAGE_BIN);
+  rc |= launch<MAXJ>(x, k_init<RES, MAXJ>, 256, J, n, c(G::init_blocks));
+  rc |= launch<MAXJ>(x, k_bin<RES, MAXJ>, 256, J, n, [](const JobArg& a) { return nblk(a.P, kBinChunk); });
+  rc |= launch<MAXJ>(x, k_scan<RES, MAXJ>, 1024, J, n, c(1));
+  rc |= launch<MAXJ>(x, k_scatter<RES, MAXJ>, 256, J, n, [](const JobArg& a) { return nblk(a.P, 256); });
+  x.end(STAGE_BIN);
   x.begin(STAGE_P1);
-  hipLaunchKernelGGL((k_splat_r2c<RES, MODE_SPLAT>), dim3(3 * G::rows), dim3(G::BR), 0, x.stream, sv.sorted, sv.off,
-                     (const float*)nullptr, (const BwdScalars*)nullptr, x.tw, w.X, (float*)nullptr);
+  rc |= launch<MAXJ>(x, k_splat_r2c<RES, MODE_SPLAT, MAXJ>, G::BR, J, n, c(3 * G::rows));
   x.end(STAGE_P1);
   x.begin(STAGE_P2);
-  hipLaunchKernelGGL((k_axis1_fwd<RES, true>), dim3(2 * G::cols), dim3(G::BC), 0, x.stream, w.X, w.Y, x.tw);
+  rc |= launch<MAXJ>(x, k_axis1_fwd<RES, true, MAXJ>, G::BC, J, n, c(2 * G::cols));
   x.end(STAGE_P2);
   x.begin(STAGE_P3);
-  hipLaunchKernelGGL(k_fwd_axis0<RES>, dim3(G::cols), dim3(G::BC), 0, x.stream, w.Y, w.X, x.tw, x.sigma);
+  rc |= launch<MAXJ>(x, k_fwd_axis0<RES, MAXJ>, G::BC, J, n, c(G::cols));
   x.end(STAGE_P3);
   x.begin(STAGE_P4);
-  hipLaunchKernelGGL((k_axis1_inv<RES, false>), dim3(G::cols), dim3(G::BC), 0, x.stream, w.X, w.Y, x.tw);
+  rc |= launch<MAXJ>(x, k_axis1_inv<RES, false, MAXJ>, G::BC, J, n, c(G::cols));
   x.end(STAGE_P4);
   x.begin(STAGE_P5);
-  hipLaunchKernelGGL((k_c2r_gather<RES, MODE_FWD>), dim3(G::rows), dim3(G::BR), 0, x.stream, w.Y, chi, sv.sorted,
-                     sv.off, w.part, x.tw);
+  rc |= launch<MAXJ>(x, k_c2r_gather<RES, MODE_FWD, MAXJ>, G::BR, J, n, c(G::rows));
   x.end(STAGE_P5);
-  const int nb = nblk(P, 256) > kRedBlocks ? kRedBlocks : nblk(P, 256);
   x.begin(STAGE_FWD_REDUCE);
-  hipLaunchKernelGGL(k_fwd_point_reduce, dim3(nb), dim3(256), 0, x.stream, w.part, P, sv.gradf, w.blockpart);
-  hipLaunchKernelGGL(k_fwd_scalars, dim3(1), dim3(256), 0, x.stream, w.blockpart, nb, chi, sv.hdr);
+  rc |= launch<MAXJ>(x, k_fwd_point_reduce<RES, MAXJ>, 256, J, n,
+                     [](const JobArg& a) { return nblk(a.P, 256) > kRedBlocks ? kRedBlocks : nblk(a.P, 256); });
+  rc |= launch<MAXJ>(x, k_fwd_scalars<RES, MAXJ>, 256, J, n, c(1));
   x.end(STAGE_FWD_REDUCE);
   x.begin(STAGE_NORMALIZE);
-  hipLaunchKernelGGL(k_normalize, dim3(nblk(N3 / 4, 256) > 4096 ? 4096 : nblk(N3 / 4, 256)), dim3(256), 0, x.stream,
-                     chi, N3, sv.hdr);
+  rc |= launch<MAXJ>(x, k_normalize<RES, MAXJ>, 256, J, n, c(G::norm_blocks));
   x.end(STAGE_NORMALIZE);
-  PSR_CHECK_LAUNCH();
-  return 0;
+  return rc ? -4 : 0;
 }
 
-template <int RES>
-static int launch_backward(Exec& x, int64_t P, const float* chi, const float* dchi, float* dpts, float* dnrm,
-                           const WsView& w, const SavedView& sv) {
+template <int RES, int MAXJ>
+static int seq_backward(Exec& x, const JobArg* J, int n) {
   using G = Grid<RES>;
-  constexpr int64_t N3 = (int64_t)RES * RES * RES;
-  const int nbr = nblk(N3 / 4, 256) > kRedBlocks ? kRedBlocks : nblk(N3 / 4, 256);
+  int rc = 0;
+  auto c = [](int v) { return [v](const JobArg&) { return v; }; };
   x.begin(STAGE_BWD_REDUCE);
-  hipLaunchKernelGGL(k_bwd_reduce, dim3(nbr), dim3(256), 0, x.stream, dchi, chi, N3, (double2*)w.blockpart);
-  hipLaunchKernelGGL(k_bwd_scalars, dim3(1), dim3(256), 0, x.stream, (const double2*)w.blockpart, nbr,
-                     (const SavedHeader*)sv.hdr, w.bs);
+  rc |= launch<MAXJ>(x, k_bwd_reduce<RES, MAXJ>, 256, J, n, c(bwd_reduce_blocks<RES>()));
+  rc |= launch<MAXJ>(x, k_bwd_scalars<RES, MAXJ>, 256, J, n, c(1));
   x.end(STAGE_BWD_REDUCE);
   x.begin(STAGE_B1);
-  hipLaunchKernelGGL((k_splat_r2c<RES, MODE_BWDH>), dim3(G::rows), dim3(G::BR), 0, x.stream, sv.sorted, sv.off, dchi,
-                     (const BwdScalars*)w.bs, x.tw, w.X, (float*)nullptr);
+  rc |= launch<MAXJ>(x, k_splat_r2c<RES, MODE_BWDH, MAXJ>, G::BR, J, n, c(G::rows));
   x.end(STAGE_B1);
   x.begin(STAGE_B2);
-  hipLaunchKernelGGL((k_axis1_fwd<RES, false>), dim3(G::cols), dim3(G::BC), 0, x.stream, w.X, w.Y, x.tw);
+  rc |= launch<MAXJ>(x, k_axis1_fwd<RES, false, MAXJ>, G::BC, J, n, c(G::cols));
   x.end(STAGE_B2);
   x.begin(STAGE_B3);
-  hipLaunchKernelGGL(k_bwd_axis0<RES>, dim3(G::cols), dim3(G::BC), 0, x.stream, w.Y, w.X, x.tw, x.sigma);
+  rc |= launch<MAXJ>(x, k_bwd_axis0<RES, MAXJ>, G::BC, J, n, c(G::cols));
   x.end(STAGE_B3);
   x.begin(STAGE_B4);
-  hipLaunchKernelGGL((k_axis1_inv<RES, true>), dim3(2 * G::cols), dim3(G::BC), 0, x.stream, w.X, w.Y, x.tw);
+  rc |= launch<MAXJ>(x, k_axis1_inv<RES, true, MAXJ>, G::BC, J, n, c(2 * G::cols));
   x.end(STAGE_B4);
   x.begin(STAGE_B5);
-  hipLaunchKernelGGL((k_c2r_gather<RES, MODE_BWD>), dim3(3 * G::rows), dim3(G::BR), 0, x.stream, w.Y,
-                     (float*)nullptr, sv.sorted, sv.off, w.part, x.tw);
+  rc |= launch<MAXJ>(x, k_c2r_gather<RES, MODE_BWD, MAXJ>, G::BR, J, n, c(3 * G::rows));
   x.end(STAGE_B5);
   x.begin(STAGE_BWD_FINAL);
-  hipLaunchKernelGGL(k_bwd_point_finalize, dim3(nblk(P, 256)), dim3(256), 0, x.stream, (const float4*)w.part,
-                     (const float4*)sv.gradf, (const PointRec*)sv.sorted, (const BwdScalars*)w.bs, P, dpts, dnrm);
+  rc |= launch<MAXJ>(x, k_bwd_point_finalize<RES, MAXJ>, 256, J, n, [](const JobArg& a) { return nblk(a.P, 256); });
   x.end(STAGE_BWD_FINAL);
-  PSR_CHECK_LAUNCH();
+  return rc ? -4 : 0;
+}
+
+template <int RES>
+static int run_jobs_res(Exec& x, const JobArg* J, int n, int what) {
+  if (n == 1) {
+    if ((what & RUN_FORWARD) && seq_forward<RES, 1>(x, J, n)) return -4;
+    if ((what & RUN_BACKWARD) && seq_backward<RES, 1>(x, J, n)) return -4;
+    return 0;
+  }
+  if ((what & RUN_FORWARD) && seq_forward<RES, kMaxJobs>(x, J, n)) return -4;
+  if ((what & RUN_BACKWARD) && seq_backward<RES, kMaxJobs>(x, J, n)) return -4;
   return 0;
 }
 
 template <int RES>
-static int launch_debug_spectral(Exec& x, const float* v, float* chi_prime, const WsView& w) {
+static int debug_spectral_res(Exec& x, const JobArg& job) {
   using G = Grid<RES>;
-  hipLaunchKernelGGL((k_splat_r2c<RES, MODE_LOADV>), dim3(3 * G::rows), dim3(G::BR), 0, x.stream,
-                     (const PointRec*)nullptr, (const int*)nullptr, v, (const BwdScalars*)nullptr, x.tw, w.X,
-                     (float*)nullptr);
-  hipLaunchKernelGGL((k_axis1_fwd<RES, true>), dim3(2 * G::cols), dim3(G::BC), 0, x.stream, w.X, w.Y, x.tw);
-  hipLaunchKernelGGL(k_fwd_axis0<RES>, dim3(G::cols), dim3(G::BC), 0, x.stream, w.Y, w.X, x.tw, x.sigma);
-  hipLaunchKernelGGL((k_axis1_inv<RES, false>), dim3(G::cols), dim3(G::BC), 0, x.stream, w.X, w.Y, x.tw);
-  hipLaunchKernelGGL((k_c2r_gather<RES, MODE_DBG>), dim3(G::rows), dim3(G::BR), 0, x.stream, w.Y, chi_prime,
-                     (const PointRec*)nullptr, (const int*)nullptr, (float4*)nullptr, x.tw);
-  PSR_CHECK_LAUNCH();
-  return 0;
+  auto c = [](int v) { return [v](const JobArg&) { return v; }; };
+  int rc = 0;
+  rc |= launch<1>(x, k_splat_r2c<RES, MODE_LOADV, 1>, G::BR, &job, 1, c(3 * G::rows));
+  rc |= launch<1>(x, k_axis1_fwd<RES, true, 1>, G::BC, &job, 1, c(2 * G::cols));
+  rc |= launch<1>(x, k_fwd_axis0<RES, 1>, G::BC, &job, 1, c(G::cols));
+  rc |= launch<1>(x, k_axis1_inv<RES, false, 1>, G::BC, &job, 1, c(G::cols));
+  rc |= launch<1>(x, k_c2r_gather<RES, MODE_DBG, 1>, G::BR, &job, 1, c(G::rows));
+  return rc ? -4 : 0;
 }
 
 template <int RES>
-static int launch_debug_splat(Exec& x, const float* pts, const float* nrm, int64_t P, float* v, const WsView& w,
-                              const SavedView& sv) {
+static int debug_splat_res(Exec& x, const JobArg& job) {
   using G = Grid<RES>;
-  if (int rc = launch_bin<RES>(x, pts, nrm, P, w, sv)) return rc;
-  hipLaunchKernelGGL((k_splat_r2c<RES, MODE_VOUT>), dim3(3 * G::rows), dim3(G::BR), 0, x.stream, sv.sorted, sv.off,
-                     (const float*)nullptr, (const BwdScalars*)nullptr, x.tw, (cf*)nullptr, v);
-  PSR_CHECK_LAUNCH();
-  return 0;
+  auto c = [](int v) { return [v](const JobArg&) { return v; }; };
+  int rc = 0;
+  rc |= launch<1>(x, k_init<RES, 1>, 256, &job, 1, c(G::init_blocks));
+  rc |= launch<1>(x, k_bin<RES, 1>, 256, &job, 1, [](const JobArg& a) { return nblk(a.P, kBinChunk); });
+  rc |= launch<1>(x, k_scan<RES, 1>, 1024, &job, 1, c(1));
+  rc |= launch<1>(x, k_scatter<RES, 1>, 256, &job, 1, [](const JobArg& a) { return nblk(a.P, 256); });
+  rc |= launch<1>(x, k_splat_r2c<RES, MODE_VOUT, 1>, G::BR, &job, 1, c(3 * G::rows));
+  return rc ? -4 : 0;
 }
 
 #define PSR_DISPATCH(res, call)     \
@@ -1047,29 +1207,20 @@ static int launch_debug_splat(Exec& x, const float* pts, const float* nrm, int64
     default: return -1;             \
   }
 
-int run_forward(Exec& x, int res, const float* pts, const float* nrm, int64_t P, float* chi, const WsView& w,
-                const SavedView& sv) {
-#define CALL(R) launch_forward<R>(x, pts, nrm, P, chi, w, sv)
+int run_jobs(Exec& x, int res, const JobArg* jobs, int n, int what) {
+#define CALL(R) run_jobs_res<R>(x, jobs, n, what)
   PSR_DISPATCH(res, CALL)
 #undef CALL
 }
 
-int run_backward(Exec& x, int res, int64_t P, const float* chi, const float* dchi, float* dpts, float* dnrm,
-                 const WsView& w, const SavedView& sv) {
-#define CALL(R) launch_backward<R>(x, P, chi, dchi, dpts, dnrm, w, sv)
+int run_debug_spectral(Exec& x, int res, const JobArg& job) {
+#define CALL(R) debug_spectral_res<R>(x, job)
   PSR_DISPATCH(res, CALL)
 #undef CALL
 }
 
-int run_debug_spectral(Exec& x, int res, const float* v, float* chi_prime, const WsView& w) {
-#define CALL(R) launch_debug_spectral<R>(x, v, chi_prime, w)
-  PSR_DISPATCH(res, CALL)
-#undef CALL
-}
-
-int run_debug_splat(Exec& x, int res, const float* pts, const float* nrm, int64_t P, float* v, const WsView& w,
-                    const SavedView& sv) {
-#define CALL(R) launch_debug_splat<R>(x, pts, nrm, P, v, w, sv)
+int run_debug_splat(Exec& x, int res, const JobArg& job) {
+#define CALL(R) debug_splat_res<R>(x, job)
   PSR_DISPATCH(res, CALL)
 #undef CALL
 }
