@@ -174,10 +174,6 @@ def batch_c4(dev, torch, steps=10, warmup=3):
     """64 shapes (res 64/128, P log-uniform 1e3..5e4, seed 3), fwd+bwd with
     G = 2 chi / N (loss mean chi^2): one psr_run_batched call vs the same
     solves as sequential psr_forward/psr_backward calls on one stream."""
-    if args.mode == "serve":
-        print(json.dumps(serve_mode(dev, torch, args.requests)), flush=True)
-        return
-
     import psr_synth as S
     from paper_2106_03452_amd import _lib
     from paper_2106_03452_amd import function as F
