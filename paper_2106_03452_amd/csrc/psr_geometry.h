@@ -8,6 +8,9 @@
 #ifndef PSR_ROW_THREADS
 #define PSR_ROW_THREADS 256
 #endif
+#ifndef PSR_J0_THREADS
+#define PSR_J0_THREADS 256
+#endif
 
 namespace psr {
 
@@ -21,6 +24,10 @@ __host__ __device__ constexpr int imin(int a, int b) { return a < b ? a : b; }
 // workgroup of cols_block(res) threads.
 __host__ __device__ constexpr int tile_cols(int res) { return imin(res, PSR_COL_THREADS / plan_TPL(res)); }
 __host__ __device__ constexpr int cols_block(int res) { return tile_cols(res) * plan_TPL(res); }
+
+// The fused j0 passes (three transforms per line) may use their own tile.
+__host__ __device__ constexpr int tile_j0(int res) { return imin(res, PSR_J0_THREADS / plan_TPL(res)); }
+__host__ __device__ constexpr int j0_block(int res) { return tile_j0(res) * plan_TPL(res); }
 
 // Row passes (splat + r2c and c2r + gather along j2; half-length complex
 // lines of res/2): tile_rows(res) consecutive j1 lines of one j0 per

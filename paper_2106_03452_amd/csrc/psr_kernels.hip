@@ -291,6 +291,12 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
     }
   }
 
+  // each thread's first point record is fetched now, under the row set-up
+  float4 pre0 = make_float4(0, 0, 0, 0), pre1 = pre0;
+  if constexpr (MODE != MODE_LOADV) {
+    if (t < total) load_rec(sorted, range_pick(R, t), pre0, pre1);
+  }
+
   if constexpr (MODE == MODE_SPLAT || MODE == MODE_VOUT) {
     for (int e = t; e < TR * LS; e += BR) rows[e] = cf{0.0f, 0.0f};
   } else {
@@ -329,9 +335,8 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
     if constexpr (MODE == MODE_BWDH) alpha = bs->alpha;
     __syncthreads();
     for (int qd = t; qd < total; qd += BR) {
-      const int64_t s = range_pick(R, qd);
-      float4 p0, p1;
-      load_rec(sorted, s, p0, p1);
+      float4 p0 = pre0, p1 = pre1;
+      if (qd != t) load_rec(sorted, range_pick(R, qd), p0, p1);
       const uint32_t bb = __float_as_uint(p0.w);
       const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
       float val;
@@ -397,11 +402,10 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
 
 // Store the canonical registers of TC lines transposed: out[n][a0 + l] for
 // every element n of every line l, two lines per 16-byte store.
-template <int RES>
+template <int RES, int TC = tile_cols(RES)>
 __device__ __forceinline__ void store_transposed(cf* rows, const cf* reg, cf* __restrict__ dst, int64_t stride_n,
                                                  int l, int lt) {
-  constexpr int TC = tile_cols(RES), BC = cols_block(RES), TPL = plan_TPL(RES), E = plan_E(RES),
-                LS = lstride(RES);
+  constexpr int BC = TC * plan_TPL(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
 #pragma unroll
   for (int v = 0; v < E; ++v) rows[l * LS + pidx(lt + TPL * v)] = reg[v];
   __syncthreads();
@@ -490,12 +494,12 @@ __device__ __forceinline__ float spectral_F(const float* g1, int k0, float g12, 
 template <int RES>
 __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __restrict__ out,
                                                                const cf* __restrict__ tw, float sigma, int bid) {
-  constexpr int H = RES / 2 + 1, TC = tile_cols(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
+  constexpr int H = RES / 2 + 1, TC = tile_j0(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
   __shared__ cf rows[TC * LS];
   __shared__ cf stw[RES];
   __shared__ float g1[RES];
-  stage_table<cols_block(RES)>(stw, tw + RES, RES);
-  gauss_table<RES, cols_block(RES)>(g1, sigma);
+  stage_table<j0_block(RES)>(stw, tw + RES, RES);
+  gauss_table<RES, j0_block(RES)>(g1, sigma);
   const int tb = bid % (RES / TC);
   const int k2 = bid / (RES / TC);
   const int a0 = tb * TC;
@@ -525,7 +529,7 @@ __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __res
     }
   }
   fft<RES, +1, true, true>(reg, rows + l * LS, lt, stw);
-  store_transposed<RES>(rows, reg, out + (int64_t)k2 * RES + a0, (int64_t)H * RES, l, lt);
+  store_transposed<RES, TC>(rows, reg, out + (int64_t)k2 * RES + a0, (int64_t)H * RES, l, lt);
 }
 
 // B3: FFT along j0 of H^, then the conjugate operator -i F kappa_d H^ and the
@@ -536,12 +540,12 @@ __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __res
 template <int RES>
 __device__ __forceinline__ void b_bwd_axis0(const cf* __restrict__ in, cf* __restrict__ out,
                                                                const cf* __restrict__ tw, float sigma, int bid) {
-  constexpr int H = RES / 2 + 1, TC = tile_cols(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
+  constexpr int H = RES / 2 + 1, TC = tile_j0(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
   __shared__ cf rows[TC * LS];
   __shared__ cf stw[RES];
   __shared__ float g1[RES];
-  stage_table<cols_block(RES)>(stw, tw + RES, RES);
-  gauss_table<RES, cols_block(RES)>(g1, sigma);
+  stage_table<j0_block(RES)>(stw, tw + RES, RES);
+  gauss_table<RES, j0_block(RES)>(g1, sigma);
   const int tb = bid % (RES / TC);
   const int k2 = bid / (RES / TC);
   const int a0 = tb * TC;
@@ -562,10 +566,10 @@ __device__ __forceinline__ void b_bwd_axis0(const cf* __restrict__ in, cf* __res
     reg[v] = cf{k0f * h[v].x, k0f * h[v].y};
   }
   fft<RES, +1, true, true>(reg, rows + l * LS, lt, stw);
-  store_transposed<RES>(rows, reg, out + (int64_t)k2 * RES + a0, (int64_t)H * RES, l, lt);
+  store_transposed<RES, TC>(rows, reg, out + (int64_t)k2 * RES + a0, (int64_t)H * RES, l, lt);
   __syncthreads();
   fft<RES, +1, true, true>(h, rows + l * LS, lt, stw);
-  store_transposed<RES>(rows, h, out + ((int64_t)RES * H + k2) * RES + a0, (int64_t)H * RES, l, lt);
+  store_transposed<RES, TC>(rows, h, out + ((int64_t)RES * H + k2) * RES + a0, (int64_t)H * RES, l, lt);
 }
 
 // ---------------------------------------------------------------------------
@@ -657,6 +661,15 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
     // point touches has nothing to do (uniform across the workgroup)
     if (MODE == MODE_BWD && total == 0) return;
   }
+  // each thread's first point record is fetched now, under the grid loads
+  float4 pre0 = make_float4(0, 0, 0, 0), pre1 = pre0;
+  int64_t pre_s = 0;
+  if constexpr (MODE != MODE_DBG) {
+    if (t < total) {
+      pre_s = range_pick(R, t);
+      load_rec(sorted, pre_s, pre0, pre1);
+    }
+  }
 
   {
     constexpr int NV = H * (TR / 2);
@@ -729,9 +742,12 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
   }
   if constexpr (MODE != MODE_DBG) {
     for (int qd = t; qd < total; qd += BR) {
-      const int64_t s = range_pick(R, qd);
-      float4 p0, p1;
-      load_rec(sorted, s, p0, p1);
+      int64_t s = pre_s;
+      float4 p0 = pre0, p1 = pre1;
+      if (qd != t) {
+        s = range_pick(R, qd);
+        load_rec(sorted, s, p0, p1);
+      }
       const uint32_t bb = __float_as_uint(p0.w);
       const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
       const int n0 = b2, n1 = (b2 + 1) & (RES - 1);
@@ -982,13 +998,13 @@ __global__ __launch_bounds__(cols_block(RES)) void k_axis1_fwd(const Batch<MAXJ>
 }
 
 template <int RES, int MAXJ>
-__global__ __launch_bounds__(cols_block(RES)) void k_fwd_axis0(const Batch<MAXJ> B) {
+__global__ __launch_bounds__(j0_block(RES)) void k_fwd_axis0(const Batch<MAXJ> B) {
   PSR_JOB(RES);
   b_fwd_axis0<RES>(w.Y, w.X, B.tw, J.sigma, bid);
 }
 
 template <int RES, int MAXJ>
-__global__ __launch_bounds__(cols_block(RES)) void k_bwd_axis0(const Batch<MAXJ> B) {
+__global__ __launch_bounds__(j0_block(RES)) void k_bwd_axis0(const Batch<MAXJ> B) {
   PSR_JOB(RES);
   b_bwd_axis0<RES>(w.Y, w.X, B.tw, J.sigma, bid);
 }
@@ -1061,6 +1077,8 @@ struct Grid {
   static constexpr int H = RES / 2 + 1;
   static constexpr int rows = RES * row_tiles(RES);        // row-pass workgroups per channel
   static constexpr int cols = H * (RES / tile_cols(RES));  // column-pass workgroups per channel
+  static constexpr int j0s = H * (RES / tile_j0(RES));     // workgroups of the fused j0 passes
+  static constexpr int BJ = j0_block(RES);
   static constexpr int BR = rows_block(RES), BC = cols_block(RES);
   static constexpr int64_t N3 = (int64_t)RES * RES * RES;
   static constexpr int init_blocks = nblk_c(num_bins(RES), 256) > 64 ? 64 : nblk_c(num_bins(RES), 256);
@@ -1108,7 +1126,7 @@ static int seq_forward(Exec& x, const JobArg* J, int n) {
   rc |= launch<MAXJ>(x, k_axis1_fwd<RES, true, MAXJ>, G::BC, J, n, c(2 * G::cols));
   x.end(STAGE_P2);
   x.begin(STAGE_P3);
-  rc |= launch<MAXJ>(x, k_fwd_axis0<RES, MAXJ>, G::BC, J, n, c(G::cols));
+  rc |= launch<MAXJ>(x, k_fwd_axis0<RES, MAXJ>, G::BJ, J, n, c(G::j0s));
   x.end(STAGE_P3);
   x.begin(STAGE_P4);
   rc |= launch<MAXJ>(x, k_axis1_inv<RES, false, MAXJ>, G::BC, J, n, c(G::cols));
@@ -1143,7 +1161,7 @@ static int seq_backward(Exec& x, const JobArg* J, int n) {
   rc |= launch<MAXJ>(x, k_axis1_fwd<RES, false, MAXJ>, G::BC, J, n, c(G::cols));
   x.end(STAGE_B2);
   x.begin(STAGE_B3);
-  rc |= launch<MAXJ>(x, k_bwd_axis0<RES, MAXJ>, G::BC, J, n, c(G::cols));
+  rc |= launch<MAXJ>(x, k_bwd_axis0<RES, MAXJ>, G::BJ, J, n, c(G::j0s));
   x.end(STAGE_B3);
   x.begin(STAGE_B4);
   rc |= launch<MAXJ>(x, k_axis1_inv<RES, true, MAXJ>, G::BC, J, n, c(2 * G::cols));
@@ -1176,7 +1194,7 @@ static int debug_spectral_res(Exec& x, const JobArg& job) {
   int rc = 0;
   rc |= launch<1>(x, k_splat_r2c<RES, MODE_LOADV, 1>, G::BR, &job, 1, c(3 * G::rows));
   rc |= launch<1>(x, k_axis1_fwd<RES, true, 1>, G::BC, &job, 1, c(2 * G::cols));
-  rc |= launch<1>(x, k_fwd_axis0<RES, 1>, G::BC, &job, 1, c(G::cols));
+  rc |= launch<1>(x, k_fwd_axis0<RES, 1>, G::BJ, &job, 1, c(G::j0s));
   rc |= launch<1>(x, k_axis1_inv<RES, false, 1>, G::BC, &job, 1, c(G::cols));
   rc |= launch<1>(x, k_c2r_gather<RES, MODE_DBG, 1>, G::BR, &job, 1, c(G::rows));
   return rc ? -4 : 0;
