@@ -70,6 +70,22 @@ def b_stage(r: int, P: int) -> int:
     return 128 * r ** 3 + 72 * P
 
 
+# Kernel of each single-kernel stage, as rocprofv3 names it (res substituted).
+KERNEL_STAGES = [
+    (r"k_splat_r2c<{r}, 0,", "P1_splat_r2c"),
+    (r"k_axis1_fwd<{r}, true,", "P2_fft_j1"),
+    (r"k_fwd_axis0<{r},", "P3_fft_j0_spectral_ifft_j0"),
+    (r"k_axis1_inv<{r}, false,", "P4_ifft_j1"),
+    (r"k_c2r_gather<{r}, 0,", "P5_c2r_gather"),
+    (r"k_normalize<{r},", "normalize"),
+    (r"k_splat_r2c<{r}, 1,", "B1_cotangent_r2c"),
+    (r"k_axis1_fwd<{r}, false,", "B2_fft_j1"),
+    (r"k_bwd_axis0<{r},", "B3_fft_j0_conjop_ifft_j0"),
+    (r"k_axis1_inv<{r}, true,", "B4_ifft_j1"),
+    (r"k_c2r_gather<{r}, 1,", "B5_c2r_gather"),
+]
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2106_03452_amd", "csrc")
@@ -95,6 +111,55 @@ def traffic_from_profiles(kernel_stage: str, workload: str):
     if not st:
         return None
     return st.get("hbm_bytes_per_launch")
+
+
+def _counter_means(path: str) -> dict:
+    """Mean Counter_Value (KiB) per kernel name of a rocprofv3 --pmc CSV."""
+    import csv
+    acc = {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            a = acc.setdefault(row["Kernel_Name"], [0.0, 0])
+            a[0] += float(row["Counter_Value"])
+            a[1] += 1
+    return {k: v[0] / v[1] for k, v in acc.items()}
+
+
+def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, workload="c3_256", r=256, P=100000):
+    """HBM bytes per launch of each stage kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
+    counter reads for a plain 1 GiB device copy (bench.py --calibrate-copy).
+    Writes profiles/hbm_traffic_<workload>.json, tagged with the kernel source
+    hash so that a later kernel change voids it."""
+    gib = float(1 << 30)
+    cf, cw = _counter_means(copy_fetch_csv), _counter_means(copy_write_csv)
+    # the copy kernel is the one launch whose counters are ~1 GiB-sized
+    copy_f = max(cf.values()) * 1024.0
+    copy_w = max(cw.values()) * 1024.0
+    kf, kw = gib / copy_f, gib / copy_w
+    fe, wr = _counter_means(fetch_csv), _counter_means(write_csv)
+    sb = stage_bytes(r, P)
+    stages = {}
+    for pat, stage in KERNEL_STAGES:
+        rx = re.compile(re.escape(pat.format(r=r)).replace(r"\ ", r"\s*"))
+        names = [k for k in fe if rx.search(k)]
+        if len(names) != 1:
+            continue
+        f = fe[names[0]] * 1024.0 * kf
+        w = wr.get(names[0], 0.0) * 1024.0 * kw
+        stages[stage] = {"kernel": names[0], "fetch_bytes": round(f), "write_bytes": round(w),
+                         "hbm_bytes_per_launch": round(f + w), "algorithmic_bytes": sb[stage],
+                         "ratio_to_algorithmic": round((f + w) / sb[stage], 3)}
+    out = {"workload": workload, "kernel_source_hash": kernel_source_hash(),
+           "copy_calibration": {"fetch_counter_bytes_per_GiB_copy": round(copy_f),
+                                "write_counter_bytes_per_GiB_copy": round(copy_w),
+                                "fetch_scale": round(kf, 4), "write_scale": round(kw, 4)},
+           "stages": stages}
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_" + workload + ".json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    return out
 
 
 # --------------------------------------------------------------------------- CPU baseline
@@ -286,7 +351,13 @@ def main():
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: requests per QPS level")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (scale reference for HBM counters)")
+    ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="host only: turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE CSVs of this bench and of "
+                         "--calibrate-copy into profiles/hbm_traffic_c3_256.json")
     args = ap.parse_args()
+    if args.ingest_counters:
+        print(json.dumps(ingest_counters(*args.ingest_counters), indent=1))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X (its multi-GPU slab "
               "decomposition is a design, not part of this build). Run with --gpus 1.", file=sys.stderr)

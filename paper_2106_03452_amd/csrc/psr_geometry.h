@@ -6,7 +6,7 @@
 #define PSR_COL_THREADS 256
 #endif
 #ifndef PSR_ROW_THREADS
-#define PSR_ROW_THREADS 256
+#define PSR_ROW_THREADS 512
 #endif
 #ifndef PSR_J0_THREADS
 #define PSR_J0_THREADS 256
@@ -31,11 +31,13 @@ __host__ __device__ constexpr int j0_block(int res) { return tile_j0(res) * plan
 
 // Row passes (splat + r2c and c2r + gather along j2; half-length complex
 // lines of res/2): tile_rows(res) consecutive j1 lines of one j0 per
-// workgroup of rows_block(res) threads. Points are binned by these tiles:
-// bin = b0 * row_tiles(res) + b1 / tile_rows(res).
+// workgroup of rows_block(res) threads. Points are binned by these tiles,
+// two bins per tile (floor column b1 inside the tile, or on its last column,
+// which also reaches the next tile): bin = b0 * 2 row_tiles(res) +
+// 2 (b1 / tile_rows(res)) + (b1 is the tile's last column).
 __host__ __device__ constexpr int tile_rows(int res) { return imin(res, PSR_ROW_THREADS / plan_TPL(res / 2)); }
 __host__ __device__ constexpr int rows_block(int res) { return tile_rows(res) * plan_TPL(res / 2); }
 __host__ __device__ constexpr int row_tiles(int res) { return res / tile_rows(res); }
-__host__ __device__ constexpr int num_bins(int res) { return res * row_tiles(res); }
+__host__ __device__ constexpr int num_bins(int res) { return 2 * res * row_tiles(res); }
 
 }  // namespace psr

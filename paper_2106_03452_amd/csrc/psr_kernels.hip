@@ -44,11 +44,12 @@ __device__ __forceinline__ void load_rec(const PointRec* __restrict__ s, int64_t
   b = p[1];
 }
 
-// Point ranges (in sorted order) whose 2x2 corner lines can touch the row
-// tile (j0, j1 in [tb*TR, tb*TR + TR)): bins of floor rows b0 in {j0-1, j0}
-// and of row tiles tb-1 and tb (the last column of tile tb-1 reaches line
-// tb*TR through its +1 corner). Four disjoint ranges, unused ones empty;
-// kept in named scalars so nothing is indexed dynamically.
+// Point ranges (in sorted order) whose 2x2 corner lines touch the row tile
+// (j0, j1 in [tb*TR, tb*TR + TR)): floor rows b0 in {j0-1, j0}; in each, both
+// bins of tile tb and the last-column bin of tile tb-1 (whose +1 corner
+// reaches line tb*TR). The three bins are consecutive unless tb = 0 wraps.
+// Four disjoint ranges, unused ones empty; kept in named scalars so nothing
+// is indexed dynamically.
 struct Ranges {
   int lo[4], n[4];
   int total;
@@ -60,24 +61,24 @@ __device__ __forceinline__ Ranges tile_ranges(const int* __restrict__ off, int j
   Ranges R;
 #pragma unroll
   for (int o = 0; o < 2; ++o) {
-    const int rb = ((j0 - 1 + o) & (RES - 1)) * NT;
+    const int rb = ((j0 - 1 + o) & (RES - 1)) * 2 * NT;
     int a, b, c, d;
     if constexpr (NT == 1) {
       a = off[rb];
-      b = off[rb + 1];
+      b = off[rb + 2];
       c = 0;
       d = 0;
     } else {
       if (tb > 0) {
-        a = off[rb + tb - 1];
-        b = off[rb + tb + 1];
+        a = off[rb + 2 * tb - 1];
+        b = off[rb + 2 * tb + 2];
         c = 0;
         d = 0;
       } else {
-        a = off[rb + NT - 1];
-        b = off[rb + NT];
+        a = off[rb + 2 * NT - 1];
+        b = off[rb + 2 * NT];
         c = off[rb];
-        d = off[rb + 1];
+        d = off[rb + 2];
       }
     }
     R.lo[2 * o] = a;
@@ -172,7 +173,8 @@ __device__ __forceinline__ void b_bin(const float* __restrict__ pts, const float
       n[0] = n[1] = n[2] = 0.0f;
       anybad = true;
     }
-    const int bin = b[0] * row_tiles(RES) + b[1] / tile_rows(RES);
+    const int bin = b[0] * 2 * row_tiles(RES) + 2 * (b[1] / tile_rows(RES)) +
+                    (b[1] % tile_rows(RES) == tile_rows(RES) - 1 ? 1 : 0);
     mybin[u] = bin;
     myrank[u] = atomicAdd(&hist[bin], 1);
     PointRec r;
