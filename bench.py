@@ -60,6 +60,11 @@ def stage_bytes(r: int, P: int) -> dict:
         "B4_ifft_j1": 2 * S + 3 * S,                # 2 in, 3 out
         "B5_c2r_gather": 3 * S + 32 * P + 192 * P,  # upper bound: tiles without points are skipped
         "bwd_finalize": 192 * P + 16 * P + 32 * P + 24 * P,
+        # plane passes (two axes per kernel; 64^3 to 256^3)
+        "P12_splat_r2c_fft_j1": 32 * P + 2 * S,        # sorted points in, v~_0 and W out
+        "P45_ifft_j1_c2r_gather": S + N4 + 32 * P + 64 * P,
+        "B12_cotangent_r2c_fft_j1": N4 + 32 * P + S,
+        "B45_ifft_j1_c2r_gather": 2 * S + 32 * P + 192 * P,  # upper bound: plane parts without points are skipped
     }
 
 
@@ -83,6 +88,10 @@ KERNEL_STAGES = [
     (r"k_bwd_axis0<{r},", "B3_fft_j0_conjop_ifft_j0"),
     (r"k_axis1_inv<{r}, true,", "B4_ifft_j1"),
     (r"k_c2r_gather<{r}, 1,", "B5_c2r_gather"),
+    (r"k_plane_fwd<{r}, 0,", "P12_splat_r2c_fft_j1"),
+    (r"k_plane_inv<{r}, 0,", "P45_ifft_j1_c2r_gather"),
+    (r"k_plane_fwd<{r}, 1,", "B12_cotangent_r2c_fft_j1"),
+    (r"k_plane_inv<{r}, 1,", "B45_ifft_j1_c2r_gather"),
 ]
 
 

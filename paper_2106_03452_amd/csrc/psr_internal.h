@@ -57,6 +57,10 @@ enum Stage {
   STAGE_B4,
   STAGE_B5,
   STAGE_BWD_FINAL,
+  STAGE_P12,  // plane pass: P1 + P2 in one kernel
+  STAGE_P45,  // plane pass: P4 + P5
+  STAGE_B12,  // plane pass: B1 + B2
+  STAGE_B45,  // plane pass: B4 + B5
   NUM_STAGES
 };
 

@@ -44,41 +44,44 @@ __device__ __forceinline__ void load_rec(const PointRec* __restrict__ s, int64_t
   b = p[1];
 }
 
-// Point ranges (in sorted order) whose 2x2 corner lines touch the row tile
-// (j0, j1 in [tb*TR, tb*TR + TR)): floor rows b0 in {j0-1, j0}; in each, both
-// bins of tile tb and the last-column bin of tile tb-1 (whose +1 corner
-// reaches line tb*TR). The three bins are consecutive unless tb = 0 wraps.
-// Four disjoint ranges, unused ones empty; kept in named scalars so nothing
-// is indexed dynamically.
+// Point ranges (in sorted order) whose 2x2 corner lines touch the rows
+// j1 in [a0, a0 + SPAN) of plane j0, SPAN a whole number of row tiles:
+// floor rows b0 in {j0-1, j0}; in each, both bins of every tile of the span
+// and the last-column bin of the tile before it (whose +1 corner reaches
+// line a0). These bins are consecutive unless the span starts at tile 0 and
+// the previous tile wraps round. Four disjoint ranges, unused ones empty;
+// kept in named scalars so nothing is indexed dynamically.
 struct Ranges {
   int lo[4], n[4];
   int total;
 };
 
-template <int RES>
-__device__ __forceinline__ Ranges tile_ranges(const int* __restrict__ off, int j0, int tb) {
-  constexpr int NT = row_tiles(RES);
+template <int RES, int SPAN>
+__device__ __forceinline__ Ranges span_ranges(const int* __restrict__ off, int j0, int a0) {
+  constexpr int NT = row_tiles(RES), TR = tile_rows(RES), ST = SPAN / TR;
+  static_assert(SPAN % TR == 0 && ST <= NT, "a span is a whole number of row tiles");
+  const int tbA = a0 / TR, tbB = tbA + ST;
   Ranges R;
 #pragma unroll
   for (int o = 0; o < 2; ++o) {
     const int rb = ((j0 - 1 + o) & (RES - 1)) * 2 * NT;
     int a, b, c, d;
-    if constexpr (NT == 1) {
+    if constexpr (ST == NT) {
       a = off[rb];
-      b = off[rb + 2];
+      b = off[rb + 2 * NT];
       c = 0;
       d = 0;
     } else {
-      if (tb > 0) {
-        a = off[rb + 2 * tb - 1];
-        b = off[rb + 2 * tb + 2];
+      if (tbA > 0) {
+        a = off[rb + 2 * tbA - 1];
+        b = off[rb + 2 * tbB];
         c = 0;
         d = 0;
       } else {
         a = off[rb + 2 * NT - 1];
         b = off[rb + 2 * NT];
         c = off[rb];
-        d = off[rb + 2];
+        d = off[rb + 2 * tbB];
       }
     }
     R.lo[2 * o] = a;
@@ -88,6 +91,21 @@ __device__ __forceinline__ Ranges tile_ranges(const int* __restrict__ off, int j
   }
   R.total = R.n[0] + R.n[1] + R.n[2] + R.n[3];
   return R;
+}
+
+template <int RES>
+__device__ __forceinline__ Ranges tile_ranges(const int* __restrict__ off, int j0, int tb) {
+  return span_ranges<RES, tile_rows(RES)>(off, j0, tb * tile_rows(RES));
+}
+
+// Whether any point's corners reach plane j0 (floor planes j0 - 1 and j0).
+// A plane no point reaches has zero splat rows, and nothing is gathered from
+// it: passes skip reading or writing what only such planes would use.
+template <int RES>
+__device__ __forceinline__ bool plane_live(const int* __restrict__ off, int j0) {
+  constexpr int NB = 2 * row_tiles(RES);  // bins per floor plane
+  const int r0 = ((j0 - 1) & (RES - 1)) * NB, r1 = j0 * NB;
+  return (off[r0 + NB] - off[r0]) + (off[r1 + NB] - off[r1]) > 0;
 }
 
 // Sorted index of the q-th point of the ranges (q < R.total).
@@ -283,6 +301,8 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
   if constexpr (MODE != MODE_LOADV) R = tile_ranges<RES>(off, j0, tb);
   const int total = R.total;
   if constexpr (MODE == MODE_SPLAT) {
+    // no point reaches the plane: P2 takes its lines as zero without reading them
+    if (!plane_live<RES>(off, j0)) return;
     // no point touches this tile: its rows and their spectra are zero
     if (total == 0) {
       for (int e = t; e < H * (TR / 2); e += BR) {
@@ -402,17 +422,47 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
   }
 }
 
+// Load TC lines stored transposed (element n of line l at src[n * stride_n +
+// l], two lines per 16-byte load) into the LDS lines rows[l * LS + pidx(n)].
+// All global loads are issued before the LDS writes; ends with a barrier.
+template <int RES, int TC>
+__device__ __forceinline__ void load_transposed(cf* rows, const cf* __restrict__ src, int64_t stride_n) {
+  constexpr int BC = TC * plan_TPL(RES), LS = lstride(RES);
+  constexpr int NV = RES * (TC / 2), IT = (NV + BC - 1) / BC;
+  float4 buf[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * BC;
+    if (e < NV) {
+      const int l2 = 2 * (e % (TC / 2)), n = e / (TC / 2);
+      buf[it] = *reinterpret_cast<const float4*>(src + n * stride_n + l2);
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * BC;
+    if (e < NV) {
+      const int l2 = 2 * (e % (TC / 2)), n = e / (TC / 2);
+      rows[l2 * LS + pidx(n)] = cf{buf[it].x, buf[it].y};
+      rows[(l2 + 1) * LS + pidx(n)] = cf{buf[it].z, buf[it].w};
+    }
+  }
+  __syncthreads();
+}
+
 // Store the canonical registers of TC lines transposed: out[n][a0 + l] for
-// every element n of every line l, two lines per 16-byte store.
+// every element n of every line l, two lines per 16-byte store; with a mask,
+// only the elements n with keep[n] != 0.
 template <int RES, int TC = tile_cols(RES)>
 __device__ __forceinline__ void store_transposed(cf* rows, const cf* reg, cf* __restrict__ dst, int64_t stride_n,
-                                                 int l, int lt) {
+                                                 int l, int lt, const int* keep = nullptr) {
   constexpr int BC = TC * plan_TPL(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
 #pragma unroll
   for (int v = 0; v < E; ++v) rows[l * LS + pidx(lt + TPL * v)] = reg[v];
   __syncthreads();
   for (int e = threadIdx.x; e < RES * (TC / 2); e += BC) {
     const int l2 = 2 * (e % (TC / 2)), n = e / (TC / 2);
+    if (keep && !keep[n]) continue;
     const cf x0 = rows[l2 * LS + pidx(n)], x1 = rows[(l2 + 1) * LS + pidx(n)];
     *reinterpret_cast<float4*>(dst + n * stride_n + l2) = make_float4(x0.x, x0.y, x1.x, x1.y);
   }
@@ -425,9 +475,9 @@ __device__ __forceinline__ void store_transposed(cf* rows, const cf* reg, cf* __
 //   W = kappa_1(k1) v~_1 + kappa_2(k2) v~_2, which is all the j0 pass needs of
 //   channels 1 and 2 because their operator factors do not vary along j0.
 // ---------------------------------------------------------------------------
-template <int RES, bool MERGE>
+template <int RES, bool MERGE, bool SKIP>
 __device__ __forceinline__ void b_axis1_fwd(const cf* __restrict__ in, cf* __restrict__ out,
-                                                               const cf* __restrict__ tw, int bid) {
+                                            const cf* __restrict__ tw, const int* __restrict__ off, int bid) {
   constexpr int H = RES / 2 + 1, TC = tile_cols(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
   constexpr int64_t CH = (int64_t)H * RES * RES;  // elements per channel
   __shared__ cf rows[TC * LS];
@@ -441,21 +491,23 @@ __device__ __forceinline__ void b_axis1_fwd(const cf* __restrict__ in, cf* __res
   const int a0 = tb * TC;
   const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
   const cf* src = in + ((int64_t)k2 * RES + a0 + l) * RES;
+  // SKIP: lines of a plane no point reaches were never written; they are zero
+  const bool live = !SKIP || plane_live<RES>(off, a0 + l);
   cf reg[E];
   if (!MERGE || c == 0) {
 #pragma unroll
-    for (int v = 0; v < E; ++v) reg[v] = src[c * CH + lt + TPL * v];
+    for (int v = 0; v < E; ++v) reg[v] = live ? src[c * CH + lt + TPL * v] : cf{0.0f, 0.0f};
     fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
   } else {
     cf acc[E];
 #pragma unroll
-    for (int v = 0; v < E; ++v) reg[v] = src[2 * CH + lt + TPL * v];
+    for (int v = 0; v < E; ++v) reg[v] = live ? src[2 * CH + lt + TPL * v] : cf{0.0f, 0.0f};
     fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
     const float k2f = kappa_odd(k2, RES);
 #pragma unroll
     for (int v = 0; v < E; ++v) {
       acc[v] = cf{k2f * reg[v].x, k2f * reg[v].y};
-      reg[v] = src[CH + lt + TPL * v];
+      reg[v] = live ? src[CH + lt + TPL * v] : cf{0.0f, 0.0f};
     }
     fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
 #pragma unroll
@@ -470,7 +522,8 @@ __device__ __forceinline__ void b_axis1_fwd(const cf* __restrict__ in, cf* __res
 // ---------------------------------------------------------------------------
 // P3: FFT along j0 of the 3 channels, chi~ = i F(k) sum_d kappa_d^odd v~_d
 // with F = g / (-2 pi |kappa|^2) / N (main Eq. 3; the inverse's 1/N folded
-// in), then inverse FFT along k0. B[3][k1][k2][j0] -> C[j0][k2][k1].
+// in), then inverse FFT along k0. B[2][k1][k2][j0] (or C[2][j0][k2][k1] after
+// a plane pass, IN_C) -> C[1][j0][k2][k1].
 // ---------------------------------------------------------------------------
 // Separable Gaussian of main Eq. 3: g(k) = g1(k0) g1(k1) g1(k2) with
 // g1(k) = exp(-2 sigma^2 kappa(k)^2 / r^2); one table of RES floats per
@@ -493,7 +546,7 @@ __device__ __forceinline__ float spectral_F(const float* g1, int k0, float g12, 
   return K2 == 0.0f ? 0.0f : g1[k0] * g12 * c / K2;
 }
 
-template <int RES>
+template <int RES, bool IN_C>
 __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __restrict__ out,
                                                                const cf* __restrict__ tw, float sigma, int bid) {
   constexpr int H = RES / 2 + 1, TC = tile_j0(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
@@ -507,19 +560,29 @@ __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __res
   const int a0 = tb * TC;
   const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
   const int k1 = a0 + l;
-  const cf* src = in + ((int64_t)k1 * H + k2) * RES;
+  constexpr int64_t CH = (int64_t)H * RES * RES;
   cf acc[E], reg[E];
   // sum_d kappa_d v~_d = kappa_0(k0) FFT_j0(v~_0) + FFT_j0(W)
+  if constexpr (IN_C) {
+    const cf* src = in + (int64_t)k2 * RES + a0;  // element j0 of line k1 at src[j0 H RES + l]
+    load_transposed<RES, TC>(rows, src, (int64_t)H * RES);
+    fft<RES, -1, false, true>(reg, rows + l * LS, lt, stw);
 #pragma unroll
-  for (int v = 0; v < E; ++v) reg[v] = src[lt + TPL * v];
-  fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
+    for (int v = 0; v < E; ++v) acc[v] = cscale(reg[v], kappa_odd(lt + TPL * v, RES));
+    load_transposed<RES, TC>(rows, src + CH, (int64_t)H * RES);
+    fft<RES, -1, false, true>(reg, rows + l * LS, lt, stw);
+  } else {
+    const cf* src = in + ((int64_t)k1 * H + k2) * RES;
 #pragma unroll
-  for (int v = 0; v < E; ++v) {
-    const float k0f = kappa_odd(lt + TPL * v, RES);
-    acc[v] = cf{k0f * reg[v].x, k0f * reg[v].y};
-    reg[v] = src[(int64_t)RES * H * RES + lt + TPL * v];
+    for (int v = 0; v < E; ++v) reg[v] = src[lt + TPL * v];
+    fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
+#pragma unroll
+    for (int v = 0; v < E; ++v) {
+      acc[v] = cscale(reg[v], kappa_odd(lt + TPL * v, RES));
+      reg[v] = src[CH + lt + TPL * v];
+    }
+    fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
   }
-  fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
   {
     const float g12 = g1[k1] * g1[k2];
     const float q12 = kappa_of(k1, RES) * kappa_of(k1, RES) + kappa_of(k2, RES) * kappa_of(k2, RES);
@@ -538,26 +601,35 @@ __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __res
 // inverse FFT along k0. Channel 0 carries kappa_0(k0); channels 1 and 2 only
 // differ by the constants kappa_1(k1), kappa_2(k2) along the line, so one
 // unscaled channel U = IFFT_k0(-i F H^) serves both (kappa_1 is applied in
-// the k1 pass, kappa_2 in the k2 pass). B[k1][k2][j0] -> C[2][j0][k2][k1].
-template <int RES>
+// the k1 pass, kappa_2 in the k2 pass). B[1][k1][k2][j0] (or C[1][j0][k2][k1],
+// IN_C) -> C[2][j0][k2][k1].
+template <int RES, bool IN_C>
 __device__ __forceinline__ void b_bwd_axis0(const cf* __restrict__ in, cf* __restrict__ out,
-                                                               const cf* __restrict__ tw, float sigma, int bid) {
+                                            const cf* __restrict__ tw, float sigma, const int* __restrict__ off,
+                                            int bid) {
   constexpr int H = RES / 2 + 1, TC = tile_j0(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
   __shared__ cf rows[TC * LS];
   __shared__ cf stw[RES];
   __shared__ float g1[RES];
+  __shared__ int live[RES];  // planes some point reaches: the only ones the next passes read
   stage_table<j0_block(RES)>(stw, tw + RES, RES);
   gauss_table<RES, j0_block(RES)>(g1, sigma);
+  for (int e = threadIdx.x; e < RES; e += j0_block(RES)) live[e] = plane_live<RES>(off, e);
   const int tb = bid % (RES / TC);
   const int k2 = bid / (RES / TC);
   const int a0 = tb * TC;
   const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
   const int k1 = a0 + l;
-  const cf* src = in + ((int64_t)k1 * H + k2) * RES;
   cf h[E], reg[E];
+  if constexpr (IN_C) {
+    load_transposed<RES, TC>(rows, in + (int64_t)k2 * RES + a0, (int64_t)H * RES);
+    fft<RES, -1, false, true>(h, rows + l * LS, lt, stw);
+  } else {
+    const cf* src = in + ((int64_t)k1 * H + k2) * RES;
 #pragma unroll
-  for (int v = 0; v < E; ++v) h[v] = src[lt + TPL * v];
-  fft<RES, -1, true, true>(h, rows + l * LS, lt, stw);
+    for (int v = 0; v < E; ++v) h[v] = src[lt + TPL * v];
+    fft<RES, -1, true, true>(h, rows + l * LS, lt, stw);
+  }
   const float g12 = g1[k1] * g1[k2];
   const float q12 = kappa_of(k1, RES) * kappa_of(k1, RES) + kappa_of(k2, RES) * kappa_of(k2, RES);
 #pragma unroll
@@ -568,10 +640,10 @@ __device__ __forceinline__ void b_bwd_axis0(const cf* __restrict__ in, cf* __res
     reg[v] = cf{k0f * h[v].x, k0f * h[v].y};
   }
   fft<RES, +1, true, true>(reg, rows + l * LS, lt, stw);
-  store_transposed<RES, TC>(rows, reg, out + (int64_t)k2 * RES + a0, (int64_t)H * RES, l, lt);
+  store_transposed<RES, TC>(rows, reg, out + (int64_t)k2 * RES + a0, (int64_t)H * RES, l, lt, live);
   __syncthreads();
   fft<RES, +1, true, true>(h, rows + l * LS, lt, stw);
-  store_transposed<RES, TC>(rows, h, out + ((int64_t)RES * H + k2) * RES + a0, (int64_t)H * RES, l, lt);
+  store_transposed<RES, TC>(rows, h, out + ((int64_t)RES * H + k2) * RES + a0, (int64_t)H * RES, l, lt, live);
 }
 
 // ---------------------------------------------------------------------------
@@ -583,11 +655,13 @@ __device__ __forceinline__ void b_bwd_axis0(const cf* __restrict__ in, cf* __res
 // ---------------------------------------------------------------------------
 template <int RES, bool SPLIT>
 __device__ __forceinline__ void b_axis1_inv(const cf* __restrict__ in, cf* __restrict__ out,
-                                                               const cf* __restrict__ tw, int bid) {
+                                            const cf* __restrict__ tw, const int* __restrict__ off, int bid) {
   constexpr int H = RES / 2 + 1, TC = tile_cols(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
+  constexpr int NT = row_tiles(RES), TR = tile_rows(RES);
   constexpr int64_t CH = (int64_t)H * RES * RES;
   __shared__ cf rows[TC * LS];
   __shared__ cf stw[RES];
+  __shared__ int tile_live[SPLIT ? TC * NT : 1];
   stage_table<cols_block(RES)>(stw, tw + RES, RES);
   int b = bid;
   const int tb = b % (RES / TC);
@@ -599,26 +673,51 @@ __device__ __forceinline__ void b_axis1_inv(const cf* __restrict__ in, cf* __res
   const cf* src = in + c * CH + ((int64_t)j0 * H + k2) * RES;
   cf* dst = out + c * CH + ((int64_t)k2 * RES + j0) * RES;
   cf reg[E];
-  if (!SPLIT || c == 0) {
+  if constexpr (!SPLIT) {
 #pragma unroll
     for (int v = 0; v < E; ++v) reg[v] = src[lt + TPL * v];
     fft<RES, +1, true, true>(reg, rows + l * LS, lt, stw);
 #pragma unroll
     for (int v = 0; v < E; ++v) dst[lt + TPL * v] = reg[v];
   } else {
-    cf u[E];
-#pragma unroll
-    for (int v = 0; v < E; ++v) {
-      u[v] = src[lt + TPL * v];
-      const float k1f = kappa_odd(lt + TPL * v, RES);
-      reg[v] = cf{k1f * u[v].x, k1f * u[v].y};
+    // backward: B5 reads only row tiles some point touches. Lines of planes
+    // no point reaches are neither read nor written; elsewhere only the
+    // segments of touched tiles are written (the FFT's barriers publish the
+    // flags before the stores read them).
+    if (threadIdx.x < TC * NT) {
+      const int li = threadIdx.x / NT, ti = threadIdx.x % NT;
+      tile_live[threadIdx.x] = tile_ranges<RES>(off, tb * TC + li, ti).total > 0;
     }
-    fft<RES, +1, true, true>(reg, rows + l * LS, lt, stw);
+    const bool live = plane_live<RES>(off, j0);
+    if (c == 0) {
 #pragma unroll
-    for (int v = 0; v < E; ++v) dst[lt + TPL * v] = reg[v];
-    fft<RES, +1, true, true>(u, rows + l * LS, lt, stw);
+      for (int v = 0; v < E; ++v) reg[v] = live ? src[lt + TPL * v] : cf{0.0f, 0.0f};
+      fft<RES, +1, true, true>(reg, rows + l * LS, lt, stw);
 #pragma unroll
-    for (int v = 0; v < E; ++v) dst[CH + lt + TPL * v] = u[v];
+      for (int v = 0; v < E; ++v) {
+        const int j1 = lt + TPL * v;
+        if (live && tile_live[l * NT + j1 / TR]) dst[j1] = reg[v];
+      }
+    } else {
+      cf u[E];
+#pragma unroll
+      for (int v = 0; v < E; ++v) {
+        u[v] = live ? src[lt + TPL * v] : cf{0.0f, 0.0f};
+        reg[v] = cscale(u[v], kappa_odd(lt + TPL * v, RES));
+      }
+      fft<RES, +1, true, true>(reg, rows + l * LS, lt, stw);
+#pragma unroll
+      for (int v = 0; v < E; ++v) {
+        const int j1 = lt + TPL * v;
+        if (live && tile_live[l * NT + j1 / TR]) dst[j1] = reg[v];
+      }
+      fft<RES, +1, true, true>(u, rows + l * LS, lt, stw);
+#pragma unroll
+      for (int v = 0; v < E; ++v) {
+        const int j1 = lt + TPL * v;
+        if (live && tile_live[l * NT + j1 / TR]) dst[CH + j1] = u[v];
+      }
+    }
   }
 }
 
@@ -774,6 +873,431 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
           const int slot = o0 * 2 + o1;
           if constexpr (MODE == MODE_FWD) part[s * 4 + slot] = q;
           else part[(s * 4 + slot) * 3 + c] = q;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plane passes (res 64, 128, 256). One workgroup owns one j0 plane, or one
+// part of it, and runs two transform axes on chip, so the data between the
+// j2 and j1 axes never goes through HBM:
+//   forward (P12, B12): rows of the plane -> r2c along j2 (LDS) -> FFT along
+//     j1 (registers, LDS exchange) -> C[c][j0][k2][k1];
+//   inverse (P45, B45): C[c][j0][k2][k1] -> IFFT along k1 (registers) ->
+//     c2r along k2 (LDS) -> chi' rows and/or the gather at the points.
+// The k2 = 0 and k2 = r/2 columns of a real row's spectrum are both real,
+// so they travel through the j1 axis as one packed column X_0 + i X_{r/2}:
+// r/2 complex columns per plane. At 256 a plane is split in two parts (k2
+// halves forward, j1 halves inverse); each part redoes the other axis.
+// ---------------------------------------------------------------------------
+template <int RES>
+struct Plane {
+  static constexpr int M = RES / 2, H = M + 1;
+  static constexpr int KP = RES <= 128 ? 1 : 2;  // parts per plane
+  static constexpr int NCOL = M / KP;            // packed columns per part (forward) / per round (inverse)
+  static constexpr int TPL = plan_TPL(RES);      // threads per j1 line
+  static constexpr int BLOCK = NCOL * TPL;
+  static constexpr int TPR = plan_TPL(M);        // threads per half-length row
+  static constexpr int RC = BLOCK / TPR;         // rows per chunk (forward) = rows per part (inverse)
+  static constexpr int NCHUNK = RES / RC;
+  static constexpr int LSR = lstride(M), LSC = lstride(RES);
+  static constexpr int SLOTS = RC * LSR > NCOL * LSC ? RC * LSR : NCOL * LSC;
+  // waves per SIMD asked of the register allocator: two workgroups per CU
+  // where LDS allows it (at most 128 VGPRs then)
+  static constexpr int WPE = RES == 256 ? 4 : 2;
+  static_assert(plan_E(RES) == 16 && plan_E(M) == 16, "plane passes hold 16 elements per thread");
+  static_assert(NCHUNK * RC == RES && RES / KP == RC, "chunks and parts tile the plane");
+};
+
+// Where the plane passes pay: at 256 a plane needs all of LDS, one workgroup
+// per CU, and each part redoes the other axis; only the inverse forward pass
+// (one channel, no point-free skip lost) still gains there.
+__host__ __device__ constexpr bool use_plane(int res) { return res >= 64 && res <= 128; }
+__host__ __device__ constexpr bool use_plane_p45(int res) { return res >= 64 && res <= 256; }
+
+// Workgroup -> (plane j0, sub-index u < U). The U workgroups of one plane
+// get ids equal mod 8, so they are dispatched to the same XCD, close in
+// time, and its L2 serves their repeated reads of the plane.
+template <int U>
+__device__ __forceinline__ void plane_of(int bid, int& j0, int& u) {
+  const int x = bid & 7, q = bid >> 3;
+  u = q % U;
+  j0 = (q / U) * 8 + x;
+}
+
+enum { PF_SPLAT = 0, PF_BWDH = 1, PF_LOADV = 2 };
+
+// Rows [a0, a0 + RC) of plane j0 of one channel into LDS (real samples at
+// float slot 2 pidx(n/2) + (n & 1)), then the half-length FFT of each row in
+// place. PF_SPLAT: trilinear splat of normal component ch; PF_BWDH: the
+// cotangent H = s G + alpha W - Q delta_0; PF_LOADV: v_ch rows from memory.
+// Returns false, uniformly and before any barrier, when a splat span holds
+// no point (its rows and spectra are zero and LDS is left untouched).
+template <int RES, int MODE>
+__device__ __forceinline__ bool pf_rows(cf* rows, const cf* stw, const PointRec* __restrict__ sorted,
+                                        const int* __restrict__ off, const float* __restrict__ gin,
+                                        const BwdScalars* __restrict__ bs, int j0, int a0, int ch) {
+  using PL = Plane<RES>;
+  constexpr int M = PL::M, RC = PL::RC, LSR = PL::LSR, BLOCK = PL::BLOCK;
+  constexpr int64_t N3 = (int64_t)RES * RES * RES;
+  const int t = threadIdx.x;
+  float* rf = reinterpret_cast<float*>(rows);
+  Ranges R{};
+  if constexpr (MODE != PF_LOADV) R = span_ranges<RES, RC>(off, j0, a0);
+  const int total = R.total;
+  if (MODE == PF_SPLAT && total == 0) return false;
+  float4 pre0 = make_float4(0, 0, 0, 0), pre1 = pre0;
+  if constexpr (MODE != PF_LOADV) {
+    if (t < total) load_rec(sorted, range_pick(R, t), pre0, pre1);
+  }
+  if constexpr (MODE == PF_SPLAT) {
+    for (int e = t; e < RC * LSR; e += BLOCK) rows[e] = cf{0.0f, 0.0f};
+  } else {
+    float sg = 1.0f, q = 0.0f;
+    if constexpr (MODE == PF_BWDH) {
+      sg = bs->s;
+      q = bs->q;
+    }
+    // the RC rows are one contiguous run of RC * RES floats
+    constexpr int NV = RC * M / 2;  // float4 = two complex slots
+    constexpr int IT = (NV + BLOCK - 1) / BLOCK;
+    const float4* g4 =
+        reinterpret_cast<const float4*>(gin + (MODE == PF_LOADV ? ch * N3 : 0) + ((int64_t)j0 * RES + a0) * RES);
+    float4 buf[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * BLOCK;
+      if (e < NV) buf[it] = g4[e];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * BLOCK;
+      if (e < NV) {
+        const int mm = (2 * e) % M, l = (2 * e) / M;
+        cf z0{buf[it].x * sg, buf[it].y * sg}, z1{buf[it].z * sg, buf[it].w * sg};
+        if constexpr (MODE == PF_BWDH) {
+          if (j0 == 0 && a0 + l == 0 && mm == 0) z0.x -= q;
+        }
+        rows[l * LSR + pidx(mm)] = z0;
+        rows[l * LSR + pidx(mm + 1)] = z1;
+      }
+    }
+  }
+  if constexpr (MODE != PF_LOADV) {
+    float alpha = 0.0f;
+    if constexpr (MODE == PF_BWDH) alpha = bs->alpha;
+    __syncthreads();
+    for (int qd = t; qd < total; qd += BLOCK) {
+      float4 p0 = pre0, p1 = pre1;
+      if (qd != t) load_rec(sorted, range_pick(R, qd), p0, p1);
+      const uint32_t bb = __float_as_uint(p0.w);
+      const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
+      float val;
+      if constexpr (MODE == PF_BWDH) val = alpha;
+      else val = ch == 0 ? p1.x : (ch == 1 ? p1.y : p1.z);
+#pragma unroll
+      for (int o0 = 0; o0 < 2; ++o0) {
+        if (((b0 + o0) & (RES - 1)) != j0) continue;
+        const float w0 = o0 ? p0.x : 1.0f - p0.x;
+#pragma unroll
+        for (int o1 = 0; o1 < 2; ++o1) {
+          const int l = (b1 + o1 - a0) & (RES - 1);
+          if (l >= RC) continue;
+          const float w01 = w0 * (o1 ? p0.y : 1.0f - p0.y);
+#pragma unroll
+          for (int o2 = 0; o2 < 2; ++o2) {
+            const int nn = (b2 + o2) & (RES - 1);
+            const float w = w01 * (o2 ? p0.z : 1.0f - p0.z);
+            atomicAdd(&rf[l * LSR * 2 + 2 * pidx(nn >> 1) + (nn & 1)], w * val);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  {
+    cf reg[16];
+    fft<M, -1, false, false>(reg, rows + (t / PL::TPR) * LSR, t % PL::TPR, stw);
+  }
+  return true;
+}
+
+// X(a0 + l, k2) of packed column kk from row l's half-length spectrum Z:
+// X_k = E_k + W_r^k O_k, E = (Z_k + Z*_{M-k}) / 2, O = (Z_k - Z*_{M-k}) / (2i);
+// kk = 0 packs the two real end values, X_0 + i X_M = (Re Z_0 + Im Z_0) +
+// i (Re Z_0 - Im Z_0).
+template <int RES>
+__device__ __forceinline__ cf pf_pick(const cf* rows, const cf* wr, int l, int kk) {
+  constexpr int M = RES / 2, LSR = lstride(M);
+  const cf* row = rows + l * LSR;
+  if (kk == 0) {
+    const cf z = row[0];
+    return cf{z.x + z.y, z.x - z.y};
+  }
+  const cf zk = row[pidx(kk)], zm = row[pidx(M - kk)];
+  const cf Ee{0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)};
+  const cf Oo{0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x)};
+  return cadd(Ee, cmul(wr[kk], Oo));
+}
+
+// P12 (MODE PF_SPLAT / PF_LOADV): channel set 0 -> v~_0, channel set 1 ->
+// W = kappa_1(k1) v~_1 + kappa_2(k2) v~_2, the two channels the j0 pass needs.
+// B12 (PF_BWDH): H^ along (j2, j1). Output C[set][j0][k2][k1].
+template <int RES, int MODE>
+__device__ __forceinline__ void b_plane_fwd(const PointRec* __restrict__ sorted, const int* __restrict__ off,
+                                            const float* __restrict__ gin, const BwdScalars* __restrict__ bs,
+                                            const cf* __restrict__ tw, cf* __restrict__ out, int bid) {
+  using PL = Plane<RES>;
+  constexpr int M = PL::M, H = PL::H, KP = PL::KP, NCOL = PL::NCOL, TPL = PL::TPL, RC = PL::RC;
+  constexpr int NCHUNK = PL::NCHUNK, LSC = PL::LSC, BLOCK = PL::BLOCK;
+  constexpr int NSET = MODE == PF_BWDH ? 1 : 2;
+  constexpr int VPC = 16 / NCHUNK;  // register elements filled per chunk
+  constexpr int64_t CH = (int64_t)H * RES * RES;
+  __shared__ cf buf[PL::SLOTS];
+  __shared__ cf stw[M];    // FFT table of length M (rows)
+  __shared__ cf ctw[RES];  // FFT table of length RES (columns); its first M + 1 entries are W_r^k for the r2c
+  stage_table<BLOCK>(stw, tw + M, M);
+  stage_table<BLOCK>(ctw, tw + RES, RES);
+  int j0, u;
+  plane_of<KP * NSET>(bid, j0, u);
+  const int part = u % KP, set = u / KP;
+  const int t = threadIdx.x, col = t / TPL, lt = t % TPL;
+  const int kk = part * NCOL + col;  // packed column index; 0 = (k2 = 0, k2 = M)
+  cf* const o = out + set * CH + (int64_t)j0 * H * RES;
+  const int nout = NCOL + (part == 0 ? 1 : 0);  // output k2 columns of this part (part 0 adds k2 = M)
+  if constexpr (MODE == PF_SPLAT) {
+    // no point touches the plane: its spectrum is zero
+    if (span_ranges<RES, RES>(off, j0, 0).total == 0) {
+      for (int e = t; e < nout * (RES / 2); e += BLOCK) {
+        const int i = e / (RES / 2), k1 = 2 * (e % (RES / 2));
+        const int k2 = i == NCOL ? M : part * NCOL + i;
+        *reinterpret_cast<float4*>(o + (int64_t)k2 * RES + k1) = make_float4(0, 0, 0, 0);
+      }
+      return;
+    }
+  }
+  cf reg[16], acc[16];
+  const int npass = set == 1 ? 2 : 1;
+  for (int pass = 0; pass < npass; ++pass) {
+    const int ch = set == 0 ? 0 : 2 - pass;  // set 1: channel 2, then channel 1
+#pragma unroll 1
+    for (int q = 0; q < NCHUNK; ++q) {
+      const int a0 = q * RC;
+      const bool any = pf_rows<RES, MODE>(buf, stw, sorted, off, gin, bs, j0, a0, ch);
+#pragma unroll
+      for (int w2 = 0; w2 < VPC; ++w2) {
+        const cf x = any ? pf_pick<RES>(buf, ctw, lt + TPL * w2, kk) : cf{0.0f, 0.0f};
+        // static register indices: chunk q fills reg[q VPC + w2]
+#pragma unroll
+        for (int qq = 0; qq < NCHUNK; ++qq)
+          if (q == qq) reg[qq * VPC + w2] = x;
+      }
+      __syncthreads();  // the rows are overwritten next
+    }
+    fft<RES, -1, true, true>(reg, buf + col * LSC, lt, ctw);
+    if (set == 1 && pass == 0) {
+      // kappa_2(k2) v~_2; zero in the packed column (kappa_2^odd vanishes at k2 = 0 and M)
+      const float k2f = kk == 0 ? 0.0f : kappa_odd(kk, RES);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = cscale(reg[v], k2f);
+    }
+  }
+  if (set == 1 && kk != 0) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) reg[v] = cadd(cscale(reg[v], kappa_odd(lt + TPL * v, RES)), acc[v]);
+  }
+  // unpack the packed column with its mirror k1 -> -k1:
+  // F_0 = (P(k) + P*(-k)) / 2, F_M = (P(k) - P*(-k)) / (2i)
+  cf* const line = buf + col * LSC;
+  if (kk == 0) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) line[pidx(lt + TPL * v)] = reg[v];
+  }
+  __syncthreads();
+  if (kk == 0) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int k = lt + TPL * v;
+      const cf pm = line[pidx((RES - k) & (RES - 1))];
+      cf f0{0.5f * (reg[v].x + pm.x), 0.5f * (reg[v].y - pm.y)};
+      cf fm{0.5f * (reg[v].y + pm.y), -0.5f * (reg[v].x - pm.x)};
+      if (set == 1) {
+        const float k1f = kappa_odd(k, RES);
+        f0 = cscale(f0, k1f);
+        fm = cscale(fm, k1f);
+      }
+      o[k] = f0;
+      o[(int64_t)M * RES + k] = fm;
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) o[(int64_t)kk * RES + lt + TPL * v] = reg[v];
+  }
+}
+
+enum { PI_FWD = 0, PI_BWD = 1, PI_DBG = 2 };
+
+// P45 (PI_FWD): chi' rows and the gather partials at the points; PI_DBG:
+// chi' rows only. B45 (PI_BWD, grid x3): g_v channel c = IFFT of V0, of
+// kappa_1 U and of kappa_2 U, gather partials only; a part no point touches
+// is skipped. Input C[c][j0][k2][k1]; part p owns rows j1 in [p RC, p RC + RC).
+template <int RES, int MODE>
+__device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __restrict__ chi_out,
+                                            const PointRec* __restrict__ sorted, const int* __restrict__ off,
+                                            float4* __restrict__ part, const cf* __restrict__ tw, int bid) {
+  using PL = Plane<RES>;
+  constexpr int M = PL::M, H = PL::H, KP = PL::KP, NCOL = PL::NCOL, TPL = PL::TPL, RC = PL::RC;
+  constexpr int LSR = PL::LSR, LSC = PL::LSC, BLOCK = PL::BLOCK, TPR = PL::TPR;
+  constexpr int NCH = MODE == PI_BWD ? 3 : 1;
+  constexpr int VK = 16 / KP;  // elements kept per round: the part's rows of the column
+  constexpr int64_t CH = (int64_t)H * RES * RES;
+  __shared__ cf buf[PL::SLOTS];
+  __shared__ cf stw[M];
+  __shared__ cf ctw[RES];
+  stage_table<BLOCK>(stw, tw + M, M);
+  stage_table<BLOCK>(ctw, tw + RES, RES);
+  float* const rf = reinterpret_cast<float*>(buf);
+  int j0, u;
+  plane_of<KP * NCH>(bid, j0, u);
+  const int p = u % KP, c = u / KP;
+  const int a0 = p * RC;
+  const int t = threadIdx.x, col = t / TPL, lt = t % TPL;
+  Ranges R{};
+  if constexpr (MODE != PI_DBG) R = span_ranges<RES, RC>(off, j0, a0);
+  const int total = R.total;
+  if (MODE == PI_BWD && total == 0) return;
+  float4 pre0 = make_float4(0, 0, 0, 0), pre1 = pre0;
+  int64_t pre_s = 0;
+  if constexpr (MODE != PI_DBG) {
+    if (t < total) {
+      pre_s = range_pick(R, t);
+      load_rec(sorted, pre_s, pre0, pre1);
+    }
+  }
+  const cf* const src = in + (MODE == PI_BWD && c > 0 ? CH : 0) + (int64_t)j0 * H * RES;
+  cf keep[KP][VK];
+#pragma unroll
+  for (int rd = 0; rd < KP; ++rd) {
+    const int kk = rd * NCOL + col;
+    cf reg[16];
+    if (kk == 0) {
+      // pack the real-signal columns k2 = 0 and M: Z = A_0 + i A_M
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const cf a = src[lt + TPL * v], b = src[(int64_t)M * RES + lt + TPL * v];
+        reg[v] = cf{a.x - b.y, a.y + b.x};
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) reg[v] = src[(int64_t)kk * RES + lt + TPL * v];
+    }
+    if (MODE == PI_BWD && c == 1) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) reg[v] = cscale(reg[v], kappa_odd(lt + TPL * v, RES));
+    }
+    if (MODE == PI_BWD && c == 2) {
+      const float k2f = kk == 0 ? 0.0f : kappa_odd(kk, RES);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) reg[v] = cscale(reg[v], k2f);
+    }
+    fft<RES, +1, true, true>(reg, buf + col * LSC, lt, ctw);
+#pragma unroll
+    for (int w2 = 0; w2 < VK; ++w2) {
+      cf x = reg[w2];
+#pragma unroll
+      for (int pp = 1; pp < KP; ++pp)
+        if (p == pp) x = reg[pp * VK + w2];
+      keep[rd][w2] = x;
+    }
+  }
+  // the part's rows into LDS (the last FFT stage ended with a barrier after
+  // its LDS reads): row l = lt + TPL w2, packed column unpacked into k2 = 0, M
+#pragma unroll
+  for (int rd = 0; rd < KP; ++rd) {
+    const int kk = rd * NCOL + col;
+#pragma unroll
+    for (int w2 = 0; w2 < VK; ++w2) {
+      cf* row = buf + (lt + TPL * w2) * LSR;
+      if (kk == 0) {
+        row[0] = cf{keep[rd][w2].x, 0.0f};
+        row[pidx(M)] = cf{keep[rd][w2].y, 0.0f};
+      } else {
+        row[pidx(kk)] = keep[rd][w2];
+      }
+    }
+  }
+  __syncthreads();
+  // Hermitian half-spectrum X[0..M] -> packed spectrum Z[0..M) of the
+  // even/odd samples: Z = (X_k + X*_{M-k}) + i (X_k - X*_{M-k}) e^{+2 pi i k/r}.
+  {
+    constexpr int NP = M / 2 + 1;
+    for (int e = t; e < RC * NP; e += BLOCK) {
+      const int k = e % NP, row = e / NP;
+      cf* rp = buf + row * LSR;
+      const cf xk = rp[pidx(k)], xm = rp[pidx(M - k)];
+      {
+        const cf Ee{xk.x + xm.x, xk.y - xm.y};
+        const cf Dd{xk.x - xm.x, xk.y + xm.y};
+        const cf w{ctw[k].x, -ctw[k].y};
+        const cf Oo = cmul(Dd, w);
+        rp[pidx(k)] = cf{Ee.x - Oo.y, Ee.y + Oo.x};
+      }
+      if (k != 0 && 2 * k != M) {
+        const cf Ee{xm.x + xk.x, xm.y - xk.y};
+        const cf Dd{xm.x - xk.x, xm.y + xk.y};
+        const cf w{ctw[M - k].x, -ctw[M - k].y};
+        const cf Oo = cmul(Dd, w);
+        rp[pidx(M - k)] = cf{Ee.x - Oo.y, Ee.y + Oo.x};
+      }
+    }
+  }
+  __syncthreads();
+  {
+    cf reg[16];
+    fft<M, +1, false, false>(reg, buf + (t / TPR) * LSR, t % TPR, stw);
+  }
+  // rows now hold real lines, sample n at float slot 2 pidx(n/2) + (n&1)
+  if constexpr (MODE != PI_BWD) {
+    for (int e = t; e < RC * M; e += BLOCK) {
+      const int l = e / M, mm = e % M;
+      const cf z = buf[l * LSR + pidx(mm)];
+      *reinterpret_cast<float2*>(chi_out + ((int64_t)j0 * RES + a0 + l) * RES + 2 * mm) = make_float2(z.x, z.y);
+    }
+  }
+  if constexpr (MODE != PI_DBG) {
+    for (int qd = t; qd < total; qd += BLOCK) {
+      int64_t s = pre_s;
+      float4 p0 = pre0, p1 = pre1;
+      if (qd != t) {
+        s = range_pick(R, qd);
+        load_rec(sorted, s, p0, p1);
+      }
+      const uint32_t bb = __float_as_uint(p0.w);
+      const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
+      const int n0 = b2, n1 = (b2 + 1) & (RES - 1);
+      const int s0 = 2 * pidx(n0 >> 1) + (n0 & 1), s1 = 2 * pidx(n1 >> 1) + (n1 & 1);
+      const float fz = p0.z;
+#pragma unroll
+      for (int o0 = 0; o0 < 2; ++o0) {
+        if (((b0 + o0) & (RES - 1)) != j0) continue;
+        const float wa = o0 ? p0.x : 1.0f - p0.x;
+        const float sa = o0 ? 1.0f : -1.0f;
+#pragma unroll
+        for (int o1 = 0; o1 < 2; ++o1) {
+          const int l = (b1 + o1 - a0) & (RES - 1);
+          if (l >= RC) continue;
+          const float wb = o1 ? p0.y : 1.0f - p0.y;
+          const float sb = o1 ? 1.0f : -1.0f;
+          const float v0 = rf[l * LSR * 2 + s0], v1 = rf[l * LSR * 2 + s1];
+          const float L = (1.0f - fz) * v0 + fz * v1;
+          const float dL = v1 - v0;
+          const float4 qv = make_float4(wa * wb * L, (float)RES * sa * wb * L, (float)RES * wa * sb * L,
+                                        (float)RES * wa * wb * dL);
+          const int slot = o0 * 2 + o1;
+          if constexpr (MODE == PI_FWD) part[s * 4 + slot] = qv;
+          else part[(s * 4 + slot) * 3 + c] = qv;
         }
       }
     }
@@ -993,28 +1517,28 @@ __global__ __launch_bounds__(rows_block(RES)) void k_splat_r2c(const Batch<MAXJ>
   b_splat_r2c<RES, MODE>(sv.sorted, sv.off, gin, w.bs, B.tw, w.X, J.aux_out, bid);
 }
 
-template <int RES, bool MERGE, int MAXJ>
+template <int RES, bool MERGE, bool SKIP, int MAXJ>
 __global__ __launch_bounds__(cols_block(RES)) void k_axis1_fwd(const Batch<MAXJ> B) {
   PSR_JOB(RES);
-  b_axis1_fwd<RES, MERGE>(w.X, w.Y, B.tw, bid);
+  b_axis1_fwd<RES, MERGE, SKIP>(w.X, w.Y, B.tw, sv.off, bid);
 }
 
 template <int RES, int MAXJ>
 __global__ __launch_bounds__(j0_block(RES)) void k_fwd_axis0(const Batch<MAXJ> B) {
   PSR_JOB(RES);
-  b_fwd_axis0<RES>(w.Y, w.X, B.tw, J.sigma, bid);
+  b_fwd_axis0<RES, use_plane(RES)>(w.Y, w.X, B.tw, J.sigma, bid);
 }
 
 template <int RES, int MAXJ>
 __global__ __launch_bounds__(j0_block(RES)) void k_bwd_axis0(const Batch<MAXJ> B) {
   PSR_JOB(RES);
-  b_bwd_axis0<RES>(w.Y, w.X, B.tw, J.sigma, bid);
+  b_bwd_axis0<RES, use_plane(RES)>(w.Y, w.X, B.tw, J.sigma, sv.off, bid);
 }
 
 template <int RES, bool SPLIT, int MAXJ>
 __global__ __launch_bounds__(cols_block(RES)) void k_axis1_inv(const Batch<MAXJ> B) {
   PSR_JOB(RES);
-  b_axis1_inv<RES, SPLIT>(w.X, w.Y, B.tw, bid);
+  b_axis1_inv<RES, SPLIT>(w.X, w.Y, B.tw, sv.off, bid);
 }
 
 template <int RES, int MODE, int MAXJ>
@@ -1022,6 +1546,22 @@ __global__ __launch_bounds__(rows_block(RES)) void k_c2r_gather(const Batch<MAXJ
   PSR_JOB(RES);
   float* out = MODE == MODE_DBG ? J.aux_out : J.chi;
   b_c2r_gather<RES, MODE>(w.Y, out, sv.sorted, sv.off, w.part, B.tw, bid);
+}
+
+template <int RES, int MODE, int MAXJ>
+__global__ __launch_bounds__(Plane<RES>::BLOCK) __attribute__((amdgpu_waves_per_eu(Plane<RES>::WPE)))
+void k_plane_fwd(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  const float* gin = MODE == PF_BWDH ? J.dchi : J.aux_in;
+  b_plane_fwd<RES, MODE>(sv.sorted, sv.off, gin, w.bs, B.tw, w.Y, bid);
+}
+
+template <int RES, int MODE, int MAXJ>
+__global__ __launch_bounds__(Plane<RES>::BLOCK) __attribute__((amdgpu_waves_per_eu(Plane<RES>::WPE)))
+void k_plane_inv(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  float* outp = MODE == PI_DBG ? J.aux_out : J.chi;
+  b_plane_inv<RES, MODE>(w.X, outp, sv.sorted, sv.off, w.part, B.tw, bid);
 }
 
 template <int RES, int MAXJ>
@@ -1121,21 +1661,33 @@ static int seq_forward(Exec& x, const JobArg* J, int n) {
   rc |= launch<MAXJ>(x, k_scan<RES, MAXJ>, 1024, J, n, c(1));
   rc |= launch<MAXJ>(x, k_scatter<RES, MAXJ>, 256, J, n, [](const JobArg& a) { return nblk(a.P, 256); });
   x.end(STAGE_BIN);
-  x.begin(STAGE_P1);
-  rc |= launch<MAXJ>(x, k_splat_r2c<RES, MODE_SPLAT, MAXJ>, G::BR, J, n, c(3 * G::rows));
-  x.end(STAGE_P1);
-  x.begin(STAGE_P2);
-  rc |= launch<MAXJ>(x, k_axis1_fwd<RES, true, MAXJ>, G::BC, J, n, c(2 * G::cols));
-  x.end(STAGE_P2);
+  if constexpr (use_plane(RES)) {
+    x.begin(STAGE_P12);
+    rc |= launch<MAXJ>(x, k_plane_fwd<RES, PF_SPLAT, MAXJ>, Plane<RES>::BLOCK, J, n, c(RES * Plane<RES>::KP * 2));
+    x.end(STAGE_P12);
+  } else {
+    x.begin(STAGE_P1);
+    rc |= launch<MAXJ>(x, k_splat_r2c<RES, MODE_SPLAT, MAXJ>, G::BR, J, n, c(3 * G::rows));
+    x.end(STAGE_P1);
+    x.begin(STAGE_P2);
+    rc |= launch<MAXJ>(x, k_axis1_fwd<RES, true, true, MAXJ>, G::BC, J, n, c(2 * G::cols));
+    x.end(STAGE_P2);
+  }
   x.begin(STAGE_P3);
   rc |= launch<MAXJ>(x, k_fwd_axis0<RES, MAXJ>, G::BJ, J, n, c(G::j0s));
   x.end(STAGE_P3);
-  x.begin(STAGE_P4);
-  rc |= launch<MAXJ>(x, k_axis1_inv<RES, false, MAXJ>, G::BC, J, n, c(G::cols));
-  x.end(STAGE_P4);
-  x.begin(STAGE_P5);
-  rc |= launch<MAXJ>(x, k_c2r_gather<RES, MODE_FWD, MAXJ>, G::BR, J, n, c(G::rows));
-  x.end(STAGE_P5);
+  if constexpr (use_plane_p45(RES)) {
+    x.begin(STAGE_P45);
+    rc |= launch<MAXJ>(x, k_plane_inv<RES, PI_FWD, MAXJ>, Plane<RES>::BLOCK, J, n, c(RES * Plane<RES>::KP));
+    x.end(STAGE_P45);
+  } else {
+    x.begin(STAGE_P4);
+    rc |= launch<MAXJ>(x, k_axis1_inv<RES, false, MAXJ>, G::BC, J, n, c(G::cols));
+    x.end(STAGE_P4);
+    x.begin(STAGE_P5);
+    rc |= launch<MAXJ>(x, k_c2r_gather<RES, MODE_FWD, MAXJ>, G::BR, J, n, c(G::rows));
+    x.end(STAGE_P5);
+  }
   x.begin(STAGE_FWD_REDUCE);
   rc |= launch<MAXJ>(x, k_fwd_point_reduce<RES, MAXJ>, 256, J, n,
                      [](const JobArg& a) { return nblk(a.P, 256) > kRedBlocks ? kRedBlocks : nblk(a.P, 256); });
@@ -1156,21 +1708,33 @@ static int seq_backward(Exec& x, const JobArg* J, int n) {
   rc |= launch<MAXJ>(x, k_bwd_reduce<RES, MAXJ>, 256, J, n, c(bwd_reduce_blocks<RES>()));
   rc |= launch<MAXJ>(x, k_bwd_scalars<RES, MAXJ>, 256, J, n, c(1));
   x.end(STAGE_BWD_REDUCE);
-  x.begin(STAGE_B1);
-  rc |= launch<MAXJ>(x, k_splat_r2c<RES, MODE_BWDH, MAXJ>, G::BR, J, n, c(G::rows));
-  x.end(STAGE_B1);
-  x.begin(STAGE_B2);
-  rc |= launch<MAXJ>(x, k_axis1_fwd<RES, false, MAXJ>, G::BC, J, n, c(G::cols));
-  x.end(STAGE_B2);
+  if constexpr (use_plane(RES)) {
+    x.begin(STAGE_B12);
+    rc |= launch<MAXJ>(x, k_plane_fwd<RES, PF_BWDH, MAXJ>, Plane<RES>::BLOCK, J, n, c(RES * Plane<RES>::KP));
+    x.end(STAGE_B12);
+  } else {
+    x.begin(STAGE_B1);
+    rc |= launch<MAXJ>(x, k_splat_r2c<RES, MODE_BWDH, MAXJ>, G::BR, J, n, c(G::rows));
+    x.end(STAGE_B1);
+    x.begin(STAGE_B2);
+    rc |= launch<MAXJ>(x, k_axis1_fwd<RES, false, false, MAXJ>, G::BC, J, n, c(G::cols));
+    x.end(STAGE_B2);
+  }
   x.begin(STAGE_B3);
   rc |= launch<MAXJ>(x, k_bwd_axis0<RES, MAXJ>, G::BJ, J, n, c(G::j0s));
   x.end(STAGE_B3);
-  x.begin(STAGE_B4);
-  rc |= launch<MAXJ>(x, k_axis1_inv<RES, true, MAXJ>, G::BC, J, n, c(2 * G::cols));
-  x.end(STAGE_B4);
-  x.begin(STAGE_B5);
-  rc |= launch<MAXJ>(x, k_c2r_gather<RES, MODE_BWD, MAXJ>, G::BR, J, n, c(3 * G::rows));
-  x.end(STAGE_B5);
+  if constexpr (use_plane(RES)) {
+    x.begin(STAGE_B45);
+    rc |= launch<MAXJ>(x, k_plane_inv<RES, PI_BWD, MAXJ>, Plane<RES>::BLOCK, J, n, c(RES * Plane<RES>::KP * 3));
+    x.end(STAGE_B45);
+  } else {
+    x.begin(STAGE_B4);
+    rc |= launch<MAXJ>(x, k_axis1_inv<RES, true, MAXJ>, G::BC, J, n, c(2 * G::cols));
+    x.end(STAGE_B4);
+    x.begin(STAGE_B5);
+    rc |= launch<MAXJ>(x, k_c2r_gather<RES, MODE_BWD, MAXJ>, G::BR, J, n, c(3 * G::rows));
+    x.end(STAGE_B5);
+  }
   x.begin(STAGE_BWD_FINAL);
   rc |= launch<MAXJ>(x, k_bwd_point_finalize<RES, MAXJ>, 256, J, n, [](const JobArg& a) { return nblk(a.P, 256); });
   x.end(STAGE_BWD_FINAL);
@@ -1194,11 +1758,19 @@ static int debug_spectral_res(Exec& x, const JobArg& job) {
   using G = Grid<RES>;
   auto c = [](int v) { return [v](const JobArg&) { return v; }; };
   int rc = 0;
-  rc |= launch<1>(x, k_splat_r2c<RES, MODE_LOADV, 1>, G::BR, &job, 1, c(3 * G::rows));
-  rc |= launch<1>(x, k_axis1_fwd<RES, true, 1>, G::BC, &job, 1, c(2 * G::cols));
+  if constexpr (use_plane(RES)) {
+    rc |= launch<1>(x, k_plane_fwd<RES, PF_LOADV, 1>, Plane<RES>::BLOCK, &job, 1, c(RES * Plane<RES>::KP * 2));
+  } else {
+    rc |= launch<1>(x, k_splat_r2c<RES, MODE_LOADV, 1>, G::BR, &job, 1, c(3 * G::rows));
+    rc |= launch<1>(x, k_axis1_fwd<RES, true, false, 1>, G::BC, &job, 1, c(2 * G::cols));
+  }
   rc |= launch<1>(x, k_fwd_axis0<RES, 1>, G::BJ, &job, 1, c(G::j0s));
-  rc |= launch<1>(x, k_axis1_inv<RES, false, 1>, G::BC, &job, 1, c(G::cols));
-  rc |= launch<1>(x, k_c2r_gather<RES, MODE_DBG, 1>, G::BR, &job, 1, c(G::rows));
+  if constexpr (use_plane_p45(RES)) {
+    rc |= launch<1>(x, k_plane_inv<RES, PI_DBG, 1>, Plane<RES>::BLOCK, &job, 1, c(RES * Plane<RES>::KP));
+  } else {
+    rc |= launch<1>(x, k_axis1_inv<RES, false, 1>, G::BC, &job, 1, c(G::cols));
+    rc |= launch<1>(x, k_c2r_gather<RES, MODE_DBG, 1>, G::BR, &job, 1, c(G::rows));
+  }
   return rc ? -4 : 0;
 }
 
