@@ -147,7 +147,7 @@ __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 // A first stage that writes LDS assumes the line is no longer being read.
 // `tw` is the table exp(-2 pi i e / L), e in [0, L).
 template <int L, int R, int NS, int DIR, bool IN_REG, bool OUT_REG>
-__device__ __forceinline__ void stage(cf* reg, cf* line, int lt, const cf* __restrict__ tw) {
+__device__ __forceinline__ void stage(cf* reg, cf* line, int lt, const cf* __restrict__ tw, int swz) {
   constexpr int E = plan_E(L), TPL = plan_TPL(L);
   constexpr int NB = E / R;
   constexpr int STRIDE = L / R;
@@ -156,7 +156,7 @@ __device__ __forceinline__ void stage(cf* reg, cf* line, int lt, const cf* __res
   for (int u = 0; u < NB; ++u) {
     const int j = lt + TPL * u;
 #pragma unroll
-    for (int m = 0; m < R; ++m) a[u][m] = IN_REG ? reg[u + m * NB] : line[pidx(j + m * STRIDE)];
+    for (int m = 0; m < R; ++m) a[u][m] = IN_REG ? reg[u + m * NB] : line[pidx(j + m * STRIDE) ^ swz];
   }
   if constexpr (!IN_REG) __syncthreads();
 #pragma unroll
@@ -176,7 +176,7 @@ __device__ __forceinline__ void stage(cf* reg, cf* line, int lt, const cf* __res
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       if constexpr (OUT_REG) reg[u + q * NB] = a[u][q];
-      else line[pidx(base + q * NS)] = a[u][q];
+      else line[pidx(base + q * NS) ^ swz] = a[u][q];
     }
   }
   if constexpr (!OUT_REG) __syncthreads();
@@ -185,29 +185,29 @@ __device__ __forceinline__ void stage(cf* reg, cf* line, int lt, const cf* __res
 // Whole length-L transform. IN_REG / OUT_REG select where the first stage
 // reads and the last stage writes (canonical registers or the LDS line).
 template <int L, int DIR, bool IN_REG, bool OUT_REG>
-__device__ __forceinline__ void fft(cf* reg, cf* line, int lt, const cf* __restrict__ tw) {
+__device__ __forceinline__ void fft(cf* reg, cf* line, int lt, const cf* __restrict__ tw, int swz = 0) {
   if constexpr (L == 4) {
-    stage<4, 4, 1, DIR, IN_REG, OUT_REG>(reg, line, lt, tw);
+    stage<4, 4, 1, DIR, IN_REG, OUT_REG>(reg, line, lt, tw, swz);
   } else if constexpr (L == 8) {
-    stage<8, 8, 1, DIR, IN_REG, OUT_REG>(reg, line, lt, tw);
+    stage<8, 8, 1, DIR, IN_REG, OUT_REG>(reg, line, lt, tw, swz);
   } else if constexpr (L == 16) {
-    stage<16, 16, 1, DIR, IN_REG, OUT_REG>(reg, line, lt, tw);
+    stage<16, 16, 1, DIR, IN_REG, OUT_REG>(reg, line, lt, tw, swz);
   } else if constexpr (L == 32) {
-    stage<32, 8, 1, DIR, IN_REG, false>(reg, line, lt, tw);
-    stage<32, 4, 8, DIR, false, OUT_REG>(reg, line, lt, tw);
+    stage<32, 8, 1, DIR, IN_REG, false>(reg, line, lt, tw, swz);
+    stage<32, 4, 8, DIR, false, OUT_REG>(reg, line, lt, tw, swz);
   } else if constexpr (L == 64) {
-    stage<64, 8, 1, DIR, IN_REG, false>(reg, line, lt, tw);
-    stage<64, 8, 8, DIR, false, OUT_REG>(reg, line, lt, tw);
+    stage<64, 8, 1, DIR, IN_REG, false>(reg, line, lt, tw, swz);
+    stage<64, 8, 8, DIR, false, OUT_REG>(reg, line, lt, tw, swz);
   } else if constexpr (L == 128) {
-    stage<128, 16, 1, DIR, IN_REG, false>(reg, line, lt, tw);
-    stage<128, 8, 16, DIR, false, OUT_REG>(reg, line, lt, tw);
+    stage<128, 16, 1, DIR, IN_REG, false>(reg, line, lt, tw, swz);
+    stage<128, 8, 16, DIR, false, OUT_REG>(reg, line, lt, tw, swz);
   } else if constexpr (L == 256) {
-    stage<256, 16, 1, DIR, IN_REG, false>(reg, line, lt, tw);
-    stage<256, 16, 16, DIR, false, OUT_REG>(reg, line, lt, tw);
+    stage<256, 16, 1, DIR, IN_REG, false>(reg, line, lt, tw, swz);
+    stage<256, 16, 16, DIR, false, OUT_REG>(reg, line, lt, tw, swz);
   } else if constexpr (L == 512) {
-    stage<512, 8, 1, DIR, IN_REG, false>(reg, line, lt, tw);
-    stage<512, 8, 8, DIR, false, false>(reg, line, lt, tw);
-    stage<512, 8, 64, DIR, false, OUT_REG>(reg, line, lt, tw);
+    stage<512, 8, 1, DIR, IN_REG, false>(reg, line, lt, tw, swz);
+    stage<512, 8, 8, DIR, false, false>(reg, line, lt, tw, swz);
+    stage<512, 8, 64, DIR, false, OUT_REG>(reg, line, lt, tw, swz);
   }
 }
 

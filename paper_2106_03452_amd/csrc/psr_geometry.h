@@ -11,6 +11,10 @@
 #ifndef PSR_J0_THREADS
 #define PSR_J0_THREADS 256
 #endif
+// Smallest grid size whose plane passes split each plane into two parts.
+#ifndef PSR_PLANE_SPLIT_MIN
+#define PSR_PLANE_SPLIT_MIN 256
+#endif
 
 namespace psr {
 
@@ -35,7 +39,11 @@ __host__ __device__ constexpr int j0_block(int res) { return tile_j0(res) * plan
 // two bins per tile (floor column b1 inside the tile, or on its last column,
 // which also reaches the next tile): bin = b0 * 2 row_tiles(res) +
 // 2 (b1 / tile_rows(res)) + (b1 is the tile's last column).
-__host__ __device__ constexpr int tile_rows(int res) { return imin(res, PSR_ROW_THREADS / plan_TPL(res / 2)); }
+__host__ __device__ constexpr int tile_rows(int res) {
+  // where a plane pass splits a plane of res <= 128 in two, bins must not be coarser than a part
+  return imin(imin(res, PSR_ROW_THREADS / plan_TPL(res / 2)),
+              (res >= PSR_PLANE_SPLIT_MIN && res <= 128) ? res / 2 : res);
+}
 __host__ __device__ constexpr int rows_block(int res) { return tile_rows(res) * plan_TPL(res / 2); }
 __host__ __device__ constexpr int row_tiles(int res) { return res / tile_rows(res); }
 __host__ __device__ constexpr int num_bins(int res) { return 2 * res * row_tiles(res); }

@@ -98,6 +98,18 @@ __device__ __forceinline__ Ranges tile_ranges(const int* __restrict__ off, int j
   return span_ranges<RES, tile_rows(RES)>(off, j0, tb * tile_rows(RES));
 }
 
+// LDS layout of the half-length rows of the row passes: row l starts at
+// l * row_ls(M), element i sits at pidx(i) ^ row_swz(M, l). At M = 128 the
+// XOR skew puts the rows one wavefront touches together on different banks,
+// both in the FFT stages (8 rows x 8 threads) and in the line-pair transposes
+// of the loads and stores (32 rows, one element).
+__host__ __device__ constexpr int row_ls(int M) { return M == 128 ? 152 : lstride(M); }
+__host__ __device__ constexpr int row_swz(int M, int l) { return M == 128 ? (l >> 1) & 15 : 0; }
+template <int M>
+__device__ __forceinline__ int rpos(int l, int i) {
+  return l * row_ls(M) + (pidx(i) ^ row_swz(M, l));
+}
+
 // Whether any point's corners reach plane j0 (floor planes j0 - 1 and j0).
 // A plane no point reaches has zero splat rows, and nothing is gathered from
 // it: passes skip reading or writing what only such planes would use.
@@ -280,7 +292,7 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
                                                               const cf* __restrict__ tw, cf* __restrict__ out,
                                                               float* __restrict__ vout, int bid) {
   constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_block(RES);
-  constexpr int TPL = plan_TPL(M), E = plan_E(M), LS = lstride(M);
+  constexpr int TPL = plan_TPL(M), E = plan_E(M), LS = row_ls(M);
   constexpr int64_t N3 = (int64_t)RES * RES * RES;
   __shared__ cf rows[TR * LS];
   __shared__ cf stw[M];      // FFT table of length M
@@ -346,8 +358,8 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
         if constexpr (MODE == MODE_BWDH) {
           if (j0 == 0 && a0 + l == 0 && mm == 0) z0.x -= q;
         }
-        rows[l * LS + pidx(mm)] = z0;
-        rows[l * LS + pidx(mm + 1)] = z1;
+        rows[rpos<M>(l, mm)] = z0;
+        rows[rpos<M>(l, mm + 1)] = z1;
       }
     }
   }
@@ -377,7 +389,7 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
           for (int o2 = 0; o2 < 2; ++o2) {
             const int nn = (b2 + o2) & (RES - 1);
             const float w = w01 * (o2 ? p0.z : 1.0f - p0.z);
-            atomicAdd(&rf[l * LS * 2 + 2 * pidx(nn >> 1) + (nn & 1)], w * val);
+            atomicAdd(&rf[2 * rpos<M>(l, nn >> 1) + (nn & 1)], w * val);
           }
         }
       }
@@ -388,13 +400,13 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
   if constexpr (MODE == MODE_VOUT) {
     for (int e = t; e < TR * RES; e += BR) {
       const int nn = e % RES, l = e / RES;
-      vout[c * N3 + ((int64_t)j0 * RES + a0 + l) * RES + nn] = rf[l * LS * 2 + 2 * pidx(nn >> 1) + (nn & 1)];
+      vout[c * N3 + ((int64_t)j0 * RES + a0 + l) * RES + nn] = rf[2 * rpos<M>(l, nn >> 1) + (nn & 1)];
     }
   } else {
     {
       cf reg[E];
       const int l = t / TPL;
-      fft<M, -1, false, false>(reg, rows + l * LS, t % TPL, stw);
+      fft<M, -1, false, false>(reg, rows + l * LS, t % TPL, stw, row_swz(M, l));
     }
     // X[k] = E_k + W_r^k O_k with E = (Z_k + Z*_{M-k})/2, O = (Z_k - Z*_{M-k})/(2i)
     for (int e = t; e < H * (TR / 2); e += BR) {
@@ -403,9 +415,8 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
       float4 o;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const cf* row = rows + (l + h) * LS;
-        const cf zk = row[pidx(k == M ? 0 : k)];
-        const cf zm = row[pidx(k == 0 ? 0 : M - k)];
+        const cf zk = rows[rpos<M>(l + h, k == M ? 0 : k)];
+        const cf zm = rows[rpos<M>(l + h, k == 0 ? 0 : M - k)];
         const cf Ee{0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)};
         const cf Oo{0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x)};
         const cf X = cadd(Ee, cmul(w, Oo));
@@ -573,13 +584,16 @@ __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __res
     fft<RES, -1, false, true>(reg, rows + l * LS, lt, stw);
   } else {
     const cf* src = in + ((int64_t)k1 * H + k2) * RES;
+    cf nxt[E];  // W's line is loaded under the first transform
 #pragma unroll
     for (int v = 0; v < E; ++v) reg[v] = src[lt + TPL * v];
+#pragma unroll
+    for (int v = 0; v < E; ++v) nxt[v] = src[CH + lt + TPL * v];
     fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
 #pragma unroll
     for (int v = 0; v < E; ++v) {
       acc[v] = cscale(reg[v], kappa_odd(lt + TPL * v, RES));
-      reg[v] = src[CH + lt + TPL * v];
+      reg[v] = nxt[v];
     }
     fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
   }
@@ -740,7 +754,7 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
                                                                float4* __restrict__ part,
                                                                const cf* __restrict__ tw, int bid) {
   constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_block(RES);
-  constexpr int TPL = plan_TPL(M), E = plan_E(M), LS = lstride(M);
+  constexpr int TPL = plan_TPL(M), E = plan_E(M), LS = row_ls(M);
   __shared__ cf rows[TR * LS];
   __shared__ cf stw[M];      // FFT table of length M
   __shared__ cf rtw[M + 1];  // W_RES^k, k in [0, M], for the c2r pre-processing
@@ -797,8 +811,8 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
           v.z *= k2f;
           v.w *= k2f;
         }
-        rows[l * LS + pidx(k)] = cf{v.x, v.y};
-        rows[(l + 1) * LS + pidx(k)] = cf{v.z, v.w};
+        rows[rpos<M>(l, k)] = cf{v.x, v.y};
+        rows[rpos<M>(l + 1, k)] = cf{v.z, v.w};
       }
     }
   }
@@ -810,34 +824,34 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
     const cf* twr = rtw;
     for (int e = t; e < TR * NP; e += BR) {
       const int k = e % NP, row = e / NP;
-      cf* rp = rows + row * LS;
-      const cf xk = rp[pidx(k)], xm = rp[pidx(M - k)];
+      const int ik = rpos<M>(row, k), im = rpos<M>(row, M - k);
+      const cf xk = rows[ik], xm = rows[im];
       {
         const cf Ee{xk.x + xm.x, xk.y - xm.y};
         const cf Dd{xk.x - xm.x, xk.y + xm.y};
         const cf w{twr[k].x, -twr[k].y};
         const cf Oo = cmul(Dd, w);
-        rp[pidx(k)] = cf{Ee.x - Oo.y, Ee.y + Oo.x};
+        rows[ik] = cf{Ee.x - Oo.y, Ee.y + Oo.x};
       }
       if (k != 0 && 2 * k != M) {
         const cf Ee{xm.x + xk.x, xm.y - xk.y};
         const cf Dd{xm.x - xk.x, xm.y + xk.y};
         const cf w{twr[M - k].x, -twr[M - k].y};
         const cf Oo = cmul(Dd, w);
-        rp[pidx(M - k)] = cf{Ee.x - Oo.y, Ee.y + Oo.x};
+        rows[im] = cf{Ee.x - Oo.y, Ee.y + Oo.x};
       }
     }
   }
   __syncthreads();
   {
     cf reg[E];
-    fft<M, +1, false, false>(reg, rows + (t / TPL) * LS, t % TPL, stw);
+    fft<M, +1, false, false>(reg, rows + (t / TPL) * LS, t % TPL, stw, row_swz(M, t / TPL));
   }
-  // rows now hold real lines, sample n at float slot 2 pidx(n/2) + (n&1)
+  // rows now hold real lines, sample n of row l at float slot 2 rpos(l, n/2) + (n&1)
   if constexpr (MODE != MODE_BWD) {
     for (int e = t; e < TR * M; e += BR) {
       const int l = e / M, mm = e % M;
-      const cf z = rows[l * LS + pidx(mm)];
+      const cf z = rows[rpos<M>(l, mm)];
       *reinterpret_cast<float2*>(chi_out + ((int64_t)j0 * RES + a0 + l) * RES + 2 * mm) = make_float2(z.x, z.y);
     }
   }
@@ -852,7 +866,7 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
       const uint32_t bb = __float_as_uint(p0.w);
       const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
       const int n0 = b2, n1 = (b2 + 1) & (RES - 1);
-      const int s0 = 2 * pidx(n0 >> 1) + (n0 & 1), s1 = 2 * pidx(n1 >> 1) + (n1 & 1);
+
       const float fz = p0.z;
 #pragma unroll
       for (int o0 = 0; o0 < 2; ++o0) {
@@ -865,7 +879,7 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
           if (l >= TR) continue;
           const float wb = o1 ? p0.y : 1.0f - p0.y;
           const float sb = o1 ? 1.0f : -1.0f;
-          const float v0 = rf[l * LS * 2 + s0], v1 = rf[l * LS * 2 + s1];
+          const float v0 = rf[2 * rpos<M>(l, n0 >> 1) + (n0 & 1)], v1 = rf[2 * rpos<M>(l, n1 >> 1) + (n1 & 1)];
           const float L = (1.0f - fz) * v0 + fz * v1;
           const float dL = v1 - v0;
           const float4 q = make_float4(wa * wb * L, (float)RES * sa * wb * L, (float)RES * wa * sb * L,
@@ -895,14 +909,14 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
 template <int RES>
 struct Plane {
   static constexpr int M = RES / 2, H = M + 1;
-  static constexpr int KP = RES <= 128 ? 1 : 2;  // parts per plane
+  static constexpr int KP = RES >= PSR_PLANE_SPLIT_MIN ? 2 : 1;  // parts per plane
   static constexpr int NCOL = M / KP;            // packed columns per part (forward) / per round (inverse)
   static constexpr int TPL = plan_TPL(RES);      // threads per j1 line
   static constexpr int BLOCK = NCOL * TPL;
   static constexpr int TPR = plan_TPL(M);        // threads per half-length row
   static constexpr int RC = BLOCK / TPR;         // rows per chunk (forward) = rows per part (inverse)
   static constexpr int NCHUNK = RES / RC;
-  static constexpr int LSR = lstride(M), LSC = lstride(RES);
+  static constexpr int LSR = row_ls(M), LSC = lstride(RES);
   static constexpr int SLOTS = RC * LSR > NCOL * LSC ? RC * LSR : NCOL * LSC;
   // waves per SIMD asked of the register allocator: two workgroups per CU
   // where LDS allows it (at most 128 VGPRs then)
@@ -930,7 +944,7 @@ __device__ __forceinline__ void plane_of(int bid, int& j0, int& u) {
 enum { PF_SPLAT = 0, PF_BWDH = 1, PF_LOADV = 2 };
 
 // Rows [a0, a0 + RC) of plane j0 of one channel into LDS (real samples at
-// float slot 2 pidx(n/2) + (n & 1)), then the half-length FFT of each row in
+// float slot 2 rpos(l, n/2) + (n & 1)), then the half-length FFT of each row in
 // place. PF_SPLAT: trilinear splat of normal component ch; PF_BWDH: the
 // cotangent H = s G + alpha W - Q delta_0; PF_LOADV: v_ch rows from memory.
 // Returns false, uniformly and before any barrier, when a splat span holds
@@ -980,8 +994,8 @@ __device__ __forceinline__ bool pf_rows(cf* rows, const cf* stw, const PointRec*
         if constexpr (MODE == PF_BWDH) {
           if (j0 == 0 && a0 + l == 0 && mm == 0) z0.x -= q;
         }
-        rows[l * LSR + pidx(mm)] = z0;
-        rows[l * LSR + pidx(mm + 1)] = z1;
+        rows[rpos<M>(l, mm)] = z0;
+        rows[rpos<M>(l, mm + 1)] = z1;
       }
     }
   }
@@ -1010,7 +1024,7 @@ __device__ __forceinline__ bool pf_rows(cf* rows, const cf* stw, const PointRec*
           for (int o2 = 0; o2 < 2; ++o2) {
             const int nn = (b2 + o2) & (RES - 1);
             const float w = w01 * (o2 ? p0.z : 1.0f - p0.z);
-            atomicAdd(&rf[l * LSR * 2 + 2 * pidx(nn >> 1) + (nn & 1)], w * val);
+            atomicAdd(&rf[2 * rpos<M>(l, nn >> 1) + (nn & 1)], w * val);
           }
         }
       }
@@ -1019,7 +1033,7 @@ __device__ __forceinline__ bool pf_rows(cf* rows, const cf* stw, const PointRec*
   __syncthreads();
   {
     cf reg[16];
-    fft<M, -1, false, false>(reg, rows + (t / PL::TPR) * LSR, t % PL::TPR, stw);
+    fft<M, -1, false, false>(reg, rows + (t / PL::TPR) * LSR, t % PL::TPR, stw, row_swz(M, t / PL::TPR));
   }
   return true;
 }
@@ -1030,13 +1044,12 @@ __device__ __forceinline__ bool pf_rows(cf* rows, const cf* stw, const PointRec*
 // i (Re Z_0 - Im Z_0).
 template <int RES>
 __device__ __forceinline__ cf pf_pick(const cf* rows, const cf* wr, int l, int kk) {
-  constexpr int M = RES / 2, LSR = lstride(M);
-  const cf* row = rows + l * LSR;
+  constexpr int M = RES / 2;
   if (kk == 0) {
-    const cf z = row[0];
+    const cf z = rows[rpos<M>(l, 0)];
     return cf{z.x + z.y, z.x - z.y};
   }
-  const cf zk = row[pidx(kk)], zm = row[pidx(M - kk)];
+  const cf zk = rows[rpos<M>(l, kk)], zm = rows[rpos<M>(l, M - kk)];
   const cf Ee{0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)};
   const cf Oo{0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x)};
   return cadd(Ee, cmul(wr[kk], Oo));
@@ -1219,12 +1232,12 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
     const int kk = rd * NCOL + col;
 #pragma unroll
     for (int w2 = 0; w2 < VK; ++w2) {
-      cf* row = buf + (lt + TPL * w2) * LSR;
+      const int l = lt + TPL * w2;
       if (kk == 0) {
-        row[0] = cf{keep[rd][w2].x, 0.0f};
-        row[pidx(M)] = cf{keep[rd][w2].y, 0.0f};
+        buf[rpos<M>(l, 0)] = cf{keep[rd][w2].x, 0.0f};
+        buf[rpos<M>(l, M)] = cf{keep[rd][w2].y, 0.0f};
       } else {
-        row[pidx(kk)] = keep[rd][w2];
+        buf[rpos<M>(l, kk)] = keep[rd][w2];
       }
     }
   }
@@ -1235,34 +1248,34 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
     constexpr int NP = M / 2 + 1;
     for (int e = t; e < RC * NP; e += BLOCK) {
       const int k = e % NP, row = e / NP;
-      cf* rp = buf + row * LSR;
-      const cf xk = rp[pidx(k)], xm = rp[pidx(M - k)];
+      const int ik = rpos<M>(row, k), im = rpos<M>(row, M - k);
+      const cf xk = buf[ik], xm = buf[im];
       {
         const cf Ee{xk.x + xm.x, xk.y - xm.y};
         const cf Dd{xk.x - xm.x, xk.y + xm.y};
         const cf w{ctw[k].x, -ctw[k].y};
         const cf Oo = cmul(Dd, w);
-        rp[pidx(k)] = cf{Ee.x - Oo.y, Ee.y + Oo.x};
+        buf[ik] = cf{Ee.x - Oo.y, Ee.y + Oo.x};
       }
       if (k != 0 && 2 * k != M) {
         const cf Ee{xm.x + xk.x, xm.y - xk.y};
         const cf Dd{xm.x - xk.x, xm.y + xk.y};
         const cf w{ctw[M - k].x, -ctw[M - k].y};
         const cf Oo = cmul(Dd, w);
-        rp[pidx(M - k)] = cf{Ee.x - Oo.y, Ee.y + Oo.x};
+        buf[im] = cf{Ee.x - Oo.y, Ee.y + Oo.x};
       }
     }
   }
   __syncthreads();
   {
     cf reg[16];
-    fft<M, +1, false, false>(reg, buf + (t / TPR) * LSR, t % TPR, stw);
+    fft<M, +1, false, false>(reg, buf + (t / TPR) * LSR, t % TPR, stw, row_swz(M, t / TPR));
   }
-  // rows now hold real lines, sample n at float slot 2 pidx(n/2) + (n&1)
+  // rows now hold real lines, sample n of row l at float slot 2 rpos(l, n/2) + (n&1)
   if constexpr (MODE != PI_BWD) {
     for (int e = t; e < RC * M; e += BLOCK) {
       const int l = e / M, mm = e % M;
-      const cf z = buf[l * LSR + pidx(mm)];
+      const cf z = buf[rpos<M>(l, mm)];
       *reinterpret_cast<float2*>(chi_out + ((int64_t)j0 * RES + a0 + l) * RES + 2 * mm) = make_float2(z.x, z.y);
     }
   }
@@ -1277,7 +1290,6 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
       const uint32_t bb = __float_as_uint(p0.w);
       const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
       const int n0 = b2, n1 = (b2 + 1) & (RES - 1);
-      const int s0 = 2 * pidx(n0 >> 1) + (n0 & 1), s1 = 2 * pidx(n1 >> 1) + (n1 & 1);
       const float fz = p0.z;
 #pragma unroll
       for (int o0 = 0; o0 < 2; ++o0) {
@@ -1290,7 +1302,7 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
           if (l >= RC) continue;
           const float wb = o1 ? p0.y : 1.0f - p0.y;
           const float sb = o1 ? 1.0f : -1.0f;
-          const float v0 = rf[l * LSR * 2 + s0], v1 = rf[l * LSR * 2 + s1];
+          const float v0 = rf[2 * rpos<M>(l, n0 >> 1) + (n0 & 1)], v1 = rf[2 * rpos<M>(l, n1 >> 1) + (n1 & 1)];
           const float L = (1.0f - fz) * v0 + fz * v1;
           const float dL = v1 - v0;
           const float4 qv = make_float4(wa * wb * L, (float)RES * sa * wb * L, (float)RES * wa * sb * L,

@@ -244,7 +244,8 @@ def config_c5(seed: int = 4, n_requests: int = 2000):
 
 
 def tiny_case(seed: int, res: int, P: int, sigma: float = 2.0, kind: str = "sphere") -> Shape:
-    """Small cases for parity tests: a sphere or a uniform cloud with random normals."""
+    """Small cases for parity tests: a sphere, a torus, a small off-centre sphere,
+    or a uniform cloud with random normals."""
     rng = rng_for(seed)
     if kind == "sphere":
         p, n = sphere(rng, P, 0.5 + rng.uniform(-0.05, 0.05, 3), rng.uniform(0.2, 0.35))
@@ -253,6 +254,9 @@ def tiny_case(seed: int, res: int, P: int, sigma: float = 2.0, kind: str = "sphe
         n = rng.standard_normal((P, 3))
     elif kind == "torus":
         p, n = torus(rng, P, 0.5 + rng.uniform(-0.05, 0.05, 3), 0.25, 0.08, random_rotation(rng))
+    elif kind == "small":
+        # a small off-centre sphere: most grid planes and row tiles hold no point
+        p, n = sphere(rng, P, np.array([0.3, 0.62, 0.45]) + rng.uniform(-0.02, 0.02, 3), 0.06)
     else:
         raise ValueError(kind)
     return Shape(res, sigma, _f32(p), _f32(n), kind=kind)

@@ -64,7 +64,7 @@ def test_splat_matches_oracle(psr, dev, res, P, kind):
     assert max_rel(v, ref) < 2e-6
 
 
-@pytest.mark.parametrize("res,sigma", [(8, 2.0), (16, 0.0), (32, 2.0), (64, 3.5), (128, 2.0)])
+@pytest.mark.parametrize("res,sigma", [(8, 2.0), (16, 0.0), (32, 2.0), (64, 3.5), (128, 2.0), (256, 2.0)])
 def test_spectral_random_field_matches_oracle(psr, dev, res, sigma):
     announce(f"spectral random res={res} sigma={sigma}")
     v = _rng(res).standard_normal((3, res, res, res)).astype(np.float32)
@@ -102,7 +102,8 @@ def test_spectral_nyquist_and_constant_vanish(psr, dev):
 
 # ------------------------------------------------------------------ forward
 CASES = [(8, 1, "uniform", 2.0), (8, 9, "uniform", 0.0), (16, 300, "sphere", 2.0), (16, 513, "uniform", 1.0),
-         (32, 2049, "torus", 2.0), (64, 4000, "sphere", 3.0), (64, 10007, "uniform", 2.0)]
+         (32, 2049, "torus", 2.0), (64, 4000, "sphere", 3.0), (64, 10007, "uniform", 2.0),
+         (64, 700, "small", 2.0), (128, 3000, "torus", 2.0), (128, 900, "small", 5.0), (256, 1200, "small", 2.0)]
 
 
 @pytest.mark.parametrize("res,P,kind,sigma", CASES)
@@ -131,7 +132,9 @@ def test_forward_c1_sphere(psr, dev):
 
 # ------------------------------------------------------------------ backward
 @pytest.mark.parametrize("res,P,kind,reading", [(8, 5, "uniform", 0), (16, 300, "torus", 0), (32, 2000, "sphere", 0),
-                                                (32, 1500, "uniform", 1), (64, 6000, "torus", 0)])
+                                                (32, 1500, "uniform", 1), (64, 6000, "torus", 0),
+                                                (64, 500, "small", 1), (128, 1500, "small", 0),
+                                                (128, 4000, "torus", 1), (256, 800, "small", 0)])
 def test_backward_matches_oracle(psr, dev, res, P, kind, reading):
     announce(f"backward res={res} P={P} kind={kind} reading={reading}")
     import paper_2106_03452_amd as p
