@@ -39,32 +39,62 @@ def half_spec_bytes(r: int) -> int:
     return r * r * (r // 2 + 1) * 8
 
 
-def stage_bytes(r: int, P: int) -> dict:
+def tile_rows(r: int) -> int:
+    """Rows of a binning tile (the library's row-pass geometry: 512-thread row
+    workgroups, 16 elements per thread of a half-length row)."""
+    return min(r, 512 // max(1, (r // 2) // 16))
+
+
+def live_fractions(points, r: int):
+    """Fractions of the j0 planes and of the (j0, row-tile) tiles that some
+    point's trilinear corners reach. The passes skip the rest (their splat is
+    zero and nothing is gathered from them), so they set the bytes those
+    passes must move."""
+    import numpy as np
+    t = np.asarray(points, dtype=np.float32).astype(np.float64)
+    u = t - np.floor(t)
+    u[u >= 1.0] = 0.0
+    b = np.clip(np.floor(u * r).astype(np.int64), 0, r - 1)
+    planes = np.zeros(r, dtype=bool)
+    planes[b[:, 0]] = True
+    planes[(b[:, 0] + 1) % r] = True
+    tr = tile_rows(r)
+    tiles = np.zeros((r, r // tr), dtype=bool)
+    for o0 in (0, 1):
+        for o1 in (0, 1):
+            tiles[(b[:, 0] + o0) % r, ((b[:, 1] + o1) % r) // tr] = True
+    return float(planes.mean()), float(tiles.mean())
+
+
+def stage_bytes(r: int, P: int, fp: float = 1.0, ft: float = 1.0) -> dict:
     """Algorithmic bytes per launch of each stage: every array the stage must
-    read once and write once (points, spectra, grids), nothing counted twice."""
+    read once and write once (points, spectra, grids), nothing counted twice.
+    fp / ft: fractions of planes / row tiles that points reach; spectra lines
+    of the other planes and tiles are neither written nor read where the
+    method leaves them zero or unused."""
     S = half_spec_bytes(r)
     N4 = 4 * r ** 3
     return {
         "bin": 24 * P + 32 * P * 2 + 8 * P,
-        "P1_splat_r2c": 32 * P + 3 * S,             # sorted points in, 3 half-spectra out
-        "P2_fft_j1": 3 * S + 2 * S,                 # 3 channels in, v~_0 and merged W out
-        "P3_fft_j0_spectral_ifft_j0": 2 * S + S,    # 2 in, chi~ (after the k0 inverse) out
+        "P1_splat_r2c": 32 * P + 3 * S * fp,           # sorted points in, 3 half-spectra of live planes out
+        "P2_fft_j1": 3 * S * fp + 2 * S,               # live lines of 3 channels in, v~_0 and merged W out
+        "P3_fft_j0_spectral_ifft_j0": 2 * S + S,       # 2 in, chi~ (after the k0 inverse) out
         "P4_ifft_j1": 2 * S,
-        "P5_c2r_gather": S + N4 + 32 * P + 64 * P,  # chi' written, gather partials
+        "P5_c2r_gather": S + N4 + 32 * P + 64 * P,     # chi' written, gather partials
         "fwd_reduce": 64 * P + 16 * P,
         "normalize": 2 * N4,
         "bwd_reduce": 2 * N4,
         "B1_cotangent_r2c": N4 + 32 * P + S,
         "B2_fft_j1": 2 * S,
-        "B3_fft_j0_conjop_ifft_j0": S + 2 * S,      # 1 in, kappa_0 channel and unscaled U out
-        "B4_ifft_j1": 2 * S + 3 * S,                # 2 in, 3 out
-        "B5_c2r_gather": 3 * S + 32 * P + 192 * P,  # upper bound: tiles without points are skipped
+        "B3_fft_j0_conjop_ifft_j0": S + 2 * S * fp,    # 1 in; kappa_0 channel and U out on live planes
+        "B4_ifft_j1": 2 * S * fp + 3 * S * ft,         # live planes in, touched tiles out
+        "B5_c2r_gather": 3 * S * ft + 32 * P + 192 * P,
         "bwd_finalize": 192 * P + 16 * P + 32 * P + 24 * P,
         # plane passes (two axes per kernel; 64^3 to 256^3)
         "P12_splat_r2c_fft_j1": 32 * P + 2 * S,        # sorted points in, v~_0 and W out
         "P45_ifft_j1_c2r_gather": S + N4 + 32 * P + 64 * P,
         "B12_cotangent_r2c_fft_j1": N4 + 32 * P + S,
-        "B45_ifft_j1_c2r_gather": 2 * S + 32 * P + 192 * P,  # upper bound: plane parts without points are skipped
+        "B45_ifft_j1_c2r_gather": 2 * S * fp + 32 * P + 192 * P,  # upper bound: plane parts without points are skipped
     }
 
 
@@ -134,7 +164,7 @@ def _counter_means(path: str) -> dict:
     return {k: v[0] / v[1] for k, v in acc.items()}
 
 
-def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, workload="c3_256", r=256, P=100000):
+def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, workload="c3_256"):
     """HBM bytes per launch of each stage kernel from two rocprofv3 --pmc runs
     (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
     counter reads for a plain 1 GiB device copy (bench.py --calibrate-copy).
@@ -147,7 +177,10 @@ def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, worklo
     copy_w = max(cw.values()) * 1024.0
     kf, kw = gib / copy_f, gib / copy_w
     fe, wr = _counter_means(fetch_csv), _counter_means(write_csv)
-    sb = stage_bytes(r, P)
+    import psr_synth as S
+    shape = S.config_c3()
+    r, P = shape.res, shape.P
+    sb = stage_bytes(r, P, *live_fractions(shape.points, r))
     stages = {}
     for pat, stage in KERNEL_STAGES:
         rx = re.compile(re.escape(pat.format(r=r)).replace(r"\ ", r"\s*"))
@@ -157,7 +190,7 @@ def ingest_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, worklo
         f = fe[names[0]] * 1024.0 * kf
         w = wr.get(names[0], 0.0) * 1024.0 * kw
         stages[stage] = {"kernel": names[0], "fetch_bytes": round(f), "write_bytes": round(w),
-                         "hbm_bytes_per_launch": round(f + w), "algorithmic_bytes": sb[stage],
+                         "hbm_bytes_per_launch": round(f + w), "algorithmic_bytes": round(sb[stage]),
                          "ratio_to_algorithmic": round((f + w) / sb[stage], 3)}
     out = {"workload": workload, "kernel_source_hash": kernel_source_hash(),
            "copy_calibration": {"fetch_counter_bytes_per_GiB_copy": round(copy_f),
@@ -422,12 +455,14 @@ def main():
     t_dom = ctx.stage_times()[dom]
     ctx.set("timers", 0)
     dom_ms = t_dom[0] / t_dom[1]
-    sb = stage_bytes(r, P)
+    fp, ft = live_fractions(shape.points, r)
+    sb = stage_bytes(r, P, fp, ft)
     achieved = sb[dom] / (dom_ms * 1e-3) / 1e9
     traffic = traffic_from_profiles(dom, "c3_256")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": dom, "algorithmic_bytes_per_launch": sb[dom], "avg_launch_ms": round(dom_ms, 5)}
+            "kernel": dom, "algorithmic_bytes_per_launch": round(sb[dom]), "avg_launch_ms": round(dom_ms, 5),
+            "live_plane_fraction": round(fp, 4), "live_tile_fraction": round(ft, 4)}
     step_bytes = b_stage(r, P)
     step_roof = {"bytes": step_bytes, "achieved_GBs": round(step_bytes / (ms * 1e-3) / 1e9, 1),
                  "frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
