@@ -36,7 +36,7 @@
  *
  * Asynchrony: psr_forward, psr_backward and psr_run_batched only enqueue
  * kernels on `stream` and return. Argument errors are reported at once and
- * nothing is launched. Data-dependent errors (non-finite coordinates, a zero
+ * nothing is launched. Data-dependent errors (non-finite coordinates or normals, a zero
  * or non-finite scale) are written to a status word inside `saved`, read with
  * psr_saved_status (which synchronises the stream); the grid is then NaN.
  */
@@ -60,7 +60,7 @@ enum {
   PSR_EDEGENERATE = -3,   /* scale c is zero or non-finite (e.g. all normals zero); chi is NaN */
   PSR_EDEVICE = -4,       /* a HIP runtime call failed */
   PSR_ENOTREADY = -5,     /* reserved */
-  PSR_ENONFINITE = -6     /* a point coordinate is NaN or Inf; chi is NaN */
+  PSR_ENONFINITE = -6     /* a point coordinate or normal component is NaN or Inf; chi is NaN */
 };
 
 #define PSR_MIN_RES 8

@@ -129,6 +129,92 @@ __device__ __forceinline__ int64_t range_pick(const Ranges& R, int q) {
   return s;
 }
 
+// Up to K point records per thread fetched ahead (thread t takes points t,
+// t + BLOCK, ... of the ranges), so the splat and gather loops find them in
+// registers instead of waiting on a dependent global load each turn.
+template <int K>
+struct Recs {
+  float4 a[K], b[K];
+  int64_t s[K];
+};
+
+template <int K, int BLOCK>
+__device__ __forceinline__ void fetch_recs(Recs<K>& r, const PointRec* __restrict__ sorted, const Ranges& R,
+                                           int t) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int q = t + k * BLOCK;
+    r.s[k] = 0;
+    r.a[k] = make_float4(0, 0, 0, 0);
+    r.b[k] = r.a[k];
+    if (q < R.total) {
+      r.s[k] = range_pick(R, q);
+      load_rec(sorted, r.s[k], r.a[k], r.b[k]);
+    }
+  }
+}
+
+// f(a, b, s) for every point this thread takes: the fetched ones, then any
+// beyond K * BLOCK loaded on the way.
+template <int K, int BLOCK, typename F>
+__device__ __forceinline__ void for_recs(const Recs<K>& r, const PointRec* __restrict__ sorted, const Ranges& R,
+                                         int t, F&& f) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    if (t + k * BLOCK < R.total) f(r.a[k], r.b[k], r.s[k]);
+  for (int q = t + K * BLOCK; q < R.total; q += BLOCK) {
+    float4 a, b;
+    const int64_t s = range_pick(R, q);
+    load_rec(sorted, s, a, b);
+    f(a, b, s);
+  }
+}
+
+// Fixed-point splat. LDS float atomics are several times slower than integer
+// ones on gfx950, so the splat of a span of rows accumulates integers: each
+// corner adds rintf(w * value * 2^S), with 2^S * T * maxabs <= 2^30, where T
+// counts the points of the span and maxabs bounds their |value|. A point adds
+// at most |value| to a vertex, once, so every partial sum stays below
+// 2^30 + T / 2 < 2^31; the step 2^-S is below 2 T maxabs / 2^30. Integer sums
+// do not depend on the order of the adds: the splat is bitwise reproducible.
+// Spans of more than kFixedMaxPoints points (where that step would approach
+// the FP32 rounding of the values) keep LDS float atomics.
+constexpr int kFixedMaxPoints = 1 << 16;
+
+// Returns 2^S for T = cnt points bounded by maxabs and sets inv = 2^-S (both
+// built from exponent bits).
+__device__ __forceinline__ float splat_scale(int cnt, float maxabs, float& inv) {
+  const float b = (float)cnt * maxabs;
+  int S = 0;
+  if (b > 0.0f) {
+    // b < 2^e with e = biased exponent - 126 (also for subnormal b); an
+    // infinite b (absurd normals) takes the smallest scale
+    const int e = ((__float_as_int(b) >> 23) & 0xff) - 126;
+    S = 30 - e;
+    S = S > 126 ? 126 : (S < -126 || e > 128 ? -126 : S);
+  }
+  inv = __int_as_float((127 - S) << 23);
+  return __int_as_float((127 + S) << 23);
+}
+
+// Maximum of m over a workgroup of BLOCK threads: each wavefront's maximum
+// goes to wmax[wave] (BLOCK < 64: one partial wavefront, shuffles stay within
+// its BLOCK lanes); block_max reads them back after the next barrier.
+template <int BLOCK>
+__device__ __forceinline__ void wave_max_store(float* wmax, float m) {
+  constexpr int W = BLOCK < 64 ? BLOCK : 64;
+#pragma unroll
+  for (int d = W / 2; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, W));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+}
+template <int BLOCK>
+__device__ __forceinline__ float block_max(const float* wmax) {
+  float m = wmax[0];
+#pragma unroll
+  for (int w = 1; w < (BLOCK + 63) / 64; ++w) m = fmaxf(m, wmax[w]);
+  return m;
+}
+
 // Copy the twiddle table of length L (exp(-2 pi i e / L), e in [0, n)) into
 // LDS; the first barrier of the caller makes it visible. Loaded at kernel
 // start so the copy overlaps the data loads instead of stalling a stage.
@@ -142,7 +228,7 @@ __device__ __forceinline__ void stage_table(cf* dst, const cf* __restrict__ src,
 // binning: counting sort of the points by row tile (b0, b1 / tile_rows)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void b_init(int* __restrict__ counts, int n, SavedHeader* __restrict__ hdr, int res,
-                       int64_t npoints, float sigma, float m, int reading, int bid, int nblocks) {
+                                       int64_t npoints, float sigma, float m, int reading, int bid, int nblocks) {
   for (int i = bid * blockDim.x + threadIdx.x; i < n; i += nblocks * blockDim.x) counts[i] = 0;
   if (bid == 0 && threadIdx.x == 0) {
     hdr->status = 0;
@@ -163,9 +249,8 @@ constexpr int kBinChunk = 1024;
 
 template <int RES>
 __device__ __forceinline__ void b_bin(const float* __restrict__ pts, const float* __restrict__ nrm,
-                                             int64_t npoints, int* __restrict__ counts,
-                                             PointRec* __restrict__ tmp, int2* __restrict__ colrank,
-                                             SavedHeader* __restrict__ hdr, int bid) {
+                                      int64_t npoints, int* __restrict__ counts, PointRec* __restrict__ tmp, int2* __restrict__ colrank,
+                                      SavedHeader* __restrict__ hdr, int bid) {
   constexpr int NB = num_bins(RES);
   constexpr int PPT = kBinChunk / 256;
   __shared__ int hist[NB];
@@ -190,6 +275,7 @@ __device__ __forceinline__ void b_bin(const float* __restrict__ pts, const float
         bad = true;
         x = 0.0f;
       }
+      if (!isfinite(n[a])) bad = true;  // the fixed-point splat needs finite values
       float uu = x - floorf(x);  // wrap into [0,1): periodic domain
       if (uu >= 1.0f) uu = 0.0f;
       const float tt = uu * (float)RES;  // exact: RES is a power of two
@@ -284,6 +370,134 @@ __device__ __forceinline__ void b_scatter(const PointRec* __restrict__ tmp, cons
 // ---------------------------------------------------------------------------
 enum { MODE_SPLAT = 0, MODE_BWDH = 1, MODE_LOADV = 2, MODE_VOUT = 3 };
 
+// Rows [a0, a0 + NROWS) of plane j0 of one channel into LDS as float samples
+// (row l, sample n at float slot 2 rpos(l, n/2) + (n & 1)). KIND 0: splat of
+// normal component ch over the points of R; KIND 1: the cotangent
+// H = s G - Q delta_0 + alpha W (W = splat of ones, G from gin); KIND 2: rows
+// of v_ch from gin. Ends with a barrier.
+template <int RES, int NROWS, int BLOCK, int KIND>
+__device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__ sorted, const Ranges& R,
+                                          const float* __restrict__ gin, const BwdScalars* __restrict__ bs, int j0,
+                                          int a0, int ch) {
+  constexpr int M = RES / 2, LS = row_ls(M);
+  constexpr int64_t N3 = (int64_t)RES * RES * RES;
+  const int t = threadIdx.x;
+  float* const rf = reinterpret_cast<float*>(rows);
+  // the NROWS rows are one contiguous run of NROWS * RES floats
+  constexpr int NV = NROWS * M / 2;  // float4 = two complex slots
+  constexpr int IT = (NV + BLOCK - 1) / BLOCK;
+  if constexpr (KIND == 2) {
+    const float4* g4 = reinterpret_cast<const float4*>(gin + ch * N3 + ((int64_t)j0 * RES + a0) * RES);
+    float4 buf[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * BLOCK;
+      if (e < NV) buf[it] = g4[e];
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * BLOCK;
+      if (e < NV) {
+        const int mm = (2 * e) % M, l = (2 * e) / M;
+        rows[rpos<M>(l, mm)] = cf{buf[it].x, buf[it].y};
+        rows[rpos<M>(l, mm + 1)] = cf{buf[it].z, buf[it].w};
+      }
+    }
+  } else {
+    // splat of normal component ch (or of unit weights: W in the backward),
+    // in fixed point unless the span is very dense; then back to floats, and
+    // in the backward H = s G - Q delta_0 + alpha W
+    __shared__ float wmax[(BLOCK + 63) / 64];
+    constexpr int KR = 4;
+    Recs<KR> recs;
+    fetch_recs<KR, BLOCK>(recs, sorted, R, t);
+    int* const ri = reinterpret_cast<int*>(rows);
+    float4 gbuf[KIND == 1 ? IT : 1];
+    if constexpr (KIND == 1) {
+      const float4* g4 = reinterpret_cast<const float4*>(gin + ((int64_t)j0 * RES + a0) * RES);
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int e = t + it * BLOCK;
+        if (e < NV) gbuf[it] = g4[e];
+      }
+    }
+    for (int e = t; e < NROWS * LS * 2; e += BLOCK) ri[e] = 0;  // integer and float zero alike
+    float m = 1.0f;
+    if constexpr (KIND == 0) {
+      m = 0.0f;
+      for_recs<KR, BLOCK>(recs, sorted, R, t, [&](const float4&, const float4& p1, int64_t) {
+        m = fmaxf(m, fabsf(ch == 0 ? p1.x : (ch == 1 ? p1.y : p1.z)));
+      });
+    }
+    wave_max_store<BLOCK>(wmax, m);
+    __syncthreads();
+    const bool fixedp = R.total <= kFixedMaxPoints;  // uniform over the workgroup
+    float inv = 1.0f;
+    const float sc = fixedp ? splat_scale(R.total, block_max<BLOCK>(wmax), inv) : 1.0f;
+    for_recs<KR, BLOCK>(recs, sorted, R, t, [&](const float4& p0, const float4& p1, int64_t) {
+      const uint32_t bb = __float_as_uint(p0.w);
+      const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
+      float val;
+      if constexpr (KIND == 1) val = 1.0f;
+      else val = ch == 0 ? p1.x : (ch == 1 ? p1.y : p1.z);
+#pragma unroll
+      for (int o0 = 0; o0 < 2; ++o0) {
+        if (((b0 + o0) & (RES - 1)) != j0) continue;
+        const float w0 = o0 ? p0.x : 1.0f - p0.x;
+#pragma unroll
+        for (int o1 = 0; o1 < 2; ++o1) {
+          const int l = (b1 + o1 - a0) & (RES - 1);
+          if (l >= NROWS) continue;
+          const float w01 = w0 * (o1 ? p0.y : 1.0f - p0.y) * val;
+#pragma unroll
+          for (int o2 = 0; o2 < 2; ++o2) {
+            const int nn = (b2 + o2) & (RES - 1);
+            const float w = w01 * (o2 ? p0.z : 1.0f - p0.z);
+            const int slot = 2 * rpos<M>(l, nn >> 1) + (nn & 1);
+            if (fixedp) atomicAdd(&ri[slot], (int)rintf(w * sc));
+            else atomicAdd(&rf[slot], w);
+          }
+        }
+      }
+    });
+    if (KIND == 1 || fixedp) {
+      __syncthreads();
+      float sg = 0.0f, q = 0.0f, alpha = 1.0f;
+      if constexpr (KIND == 1) {
+        sg = bs->s;
+        q = bs->q;
+        alpha = bs->alpha;
+      }
+      const float fac = inv * alpha;
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int e = t + it * BLOCK;
+        if (e < NV) {
+          const int mm = (2 * e) % M, l = (2 * e) / M;
+          const int i0 = 2 * rpos<M>(l, mm), i1 = 2 * rpos<M>(l, mm + 1);
+          float4 v;
+          if (fixedp) v = make_float4((float)ri[i0], (float)ri[i0 + 1], (float)ri[i1], (float)ri[i1 + 1]);
+          else v = make_float4(rf[i0], rf[i0 + 1], rf[i1], rf[i1 + 1]);
+          v = make_float4(v.x * fac, v.y * fac, v.z * fac, v.w * fac);
+          if constexpr (KIND == 1) {
+            v.x += sg * gbuf[it].x;
+            v.y += sg * gbuf[it].y;
+            v.z += sg * gbuf[it].z;
+            v.w += sg * gbuf[it].w;
+            if (j0 == 0 && a0 + l == 0 && mm == 0) v.x -= q;
+          }
+          rf[i0] = v.x;
+          rf[i0 + 1] = v.y;
+          rf[i1] = v.z;
+          rf[i1 + 1] = v.w;
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+
 template <int RES, int MODE>
 __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
                                                               const int* __restrict__ off,
@@ -325,77 +539,7 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
     }
   }
 
-  // each thread's first point record is fetched now, under the row set-up
-  float4 pre0 = make_float4(0, 0, 0, 0), pre1 = pre0;
-  if constexpr (MODE != MODE_LOADV) {
-    if (t < total) load_rec(sorted, range_pick(R, t), pre0, pre1);
-  }
-
-  if constexpr (MODE == MODE_SPLAT || MODE == MODE_VOUT) {
-    for (int e = t; e < TR * LS; e += BR) rows[e] = cf{0.0f, 0.0f};
-  } else {
-    float sg = 1.0f, q = 0.0f;
-    if constexpr (MODE == MODE_BWDH) {
-      sg = bs->s;
-      q = bs->q;
-    }
-    // the TR rows of this tile are one contiguous run of TR * RES floats
-    constexpr int NV = TR * M / 2;  // float4 = two complex slots
-    constexpr int IT = (NV + BR - 1) / BR;
-    const float4* g4 = reinterpret_cast<const float4*>(gin + c * N3 + ((int64_t)j0 * RES + a0) * RES);
-    float4 buf[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int e = t + it * BR;
-      if (e < NV) buf[it] = g4[e];
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int e = t + it * BR;
-      if (e < NV) {
-        const int mm = (2 * e) % M, l = (2 * e) / M;
-        cf z0{buf[it].x * sg, buf[it].y * sg}, z1{buf[it].z * sg, buf[it].w * sg};
-        if constexpr (MODE == MODE_BWDH) {
-          if (j0 == 0 && a0 + l == 0 && mm == 0) z0.x -= q;
-        }
-        rows[rpos<M>(l, mm)] = z0;
-        rows[rpos<M>(l, mm + 1)] = z1;
-      }
-    }
-  }
-
-  if constexpr (MODE != MODE_LOADV) {
-    float alpha = 0.0f;
-    if constexpr (MODE == MODE_BWDH) alpha = bs->alpha;
-    __syncthreads();
-    for (int qd = t; qd < total; qd += BR) {
-      float4 p0 = pre0, p1 = pre1;
-      if (qd != t) load_rec(sorted, range_pick(R, qd), p0, p1);
-      const uint32_t bb = __float_as_uint(p0.w);
-      const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
-      float val;
-      if constexpr (MODE == MODE_BWDH) val = alpha;
-      else val = c == 0 ? p1.x : (c == 1 ? p1.y : p1.z);
-#pragma unroll
-      for (int o0 = 0; o0 < 2; ++o0) {
-        if (((b0 + o0) & (RES - 1)) != j0) continue;
-        const float w0 = o0 ? p0.x : 1.0f - p0.x;
-#pragma unroll
-        for (int o1 = 0; o1 < 2; ++o1) {
-          const int l = (b1 + o1 - a0) & (RES - 1);
-          if (l >= TR) continue;
-          const float w01 = w0 * (o1 ? p0.y : 1.0f - p0.y);
-#pragma unroll
-          for (int o2 = 0; o2 < 2; ++o2) {
-            const int nn = (b2 + o2) & (RES - 1);
-            const float w = w01 * (o2 ? p0.z : 1.0f - p0.z);
-            atomicAdd(&rf[2 * rpos<M>(l, nn >> 1) + (nn & 1)], w * val);
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
+  fill_rows<RES, TR, BR, MODE == MODE_VOUT ? MODE_SPLAT : MODE>(rows, sorted, R, gin, bs, j0, a0, c);
 
   if constexpr (MODE == MODE_VOUT) {
     for (int e = t; e < TR * RES; e += BR) {
@@ -776,15 +920,10 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
     // point touches has nothing to do (uniform across the workgroup)
     if (MODE == MODE_BWD && total == 0) return;
   }
-  // each thread's first point record is fetched now, under the grid loads
-  float4 pre0 = make_float4(0, 0, 0, 0), pre1 = pre0;
-  int64_t pre_s = 0;
-  if constexpr (MODE != MODE_DBG) {
-    if (t < total) {
-      pre_s = range_pick(R, t);
-      load_rec(sorted, pre_s, pre0, pre1);
-    }
-  }
+  // the thread's point records are fetched now, under the grid loads
+  constexpr int KR = 4;
+  Recs<KR> recs;
+  if constexpr (MODE != MODE_DBG) fetch_recs<KR, BR>(recs, sorted, R, t);
 
   {
     constexpr int NV = H * (TR / 2);
@@ -856,13 +995,7 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
     }
   }
   if constexpr (MODE != MODE_DBG) {
-    for (int qd = t; qd < total; qd += BR) {
-      int64_t s = pre_s;
-      float4 p0 = pre0, p1 = pre1;
-      if (qd != t) {
-        s = range_pick(R, qd);
-        load_rec(sorted, s, p0, p1);
-      }
+    for_recs<KR, BR>(recs, sorted, R, t, [&](const float4& p0, const float4& p1, int64_t s) {
       const uint32_t bb = __float_as_uint(p0.w);
       const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
       const int n0 = b2, n1 = (b2 + 1) & (RES - 1);
@@ -889,7 +1022,7 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
           else part[(s * 4 + slot) * 3 + c] = q;
         }
       }
-    }
+    });
   }
 }
 
@@ -955,82 +1088,11 @@ __device__ __forceinline__ bool pf_rows(cf* rows, const cf* stw, const PointRec*
                                         const BwdScalars* __restrict__ bs, int j0, int a0, int ch) {
   using PL = Plane<RES>;
   constexpr int M = PL::M, RC = PL::RC, LSR = PL::LSR, BLOCK = PL::BLOCK;
-  constexpr int64_t N3 = (int64_t)RES * RES * RES;
   const int t = threadIdx.x;
-  float* rf = reinterpret_cast<float*>(rows);
   Ranges R{};
   if constexpr (MODE != PF_LOADV) R = span_ranges<RES, RC>(off, j0, a0);
-  const int total = R.total;
-  if (MODE == PF_SPLAT && total == 0) return false;
-  float4 pre0 = make_float4(0, 0, 0, 0), pre1 = pre0;
-  if constexpr (MODE != PF_LOADV) {
-    if (t < total) load_rec(sorted, range_pick(R, t), pre0, pre1);
-  }
-  if constexpr (MODE == PF_SPLAT) {
-    for (int e = t; e < RC * LSR; e += BLOCK) rows[e] = cf{0.0f, 0.0f};
-  } else {
-    float sg = 1.0f, q = 0.0f;
-    if constexpr (MODE == PF_BWDH) {
-      sg = bs->s;
-      q = bs->q;
-    }
-    // the RC rows are one contiguous run of RC * RES floats
-    constexpr int NV = RC * M / 2;  // float4 = two complex slots
-    constexpr int IT = (NV + BLOCK - 1) / BLOCK;
-    const float4* g4 =
-        reinterpret_cast<const float4*>(gin + (MODE == PF_LOADV ? ch * N3 : 0) + ((int64_t)j0 * RES + a0) * RES);
-    float4 buf[IT];
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int e = t + it * BLOCK;
-      if (e < NV) buf[it] = g4[e];
-    }
-#pragma unroll
-    for (int it = 0; it < IT; ++it) {
-      const int e = t + it * BLOCK;
-      if (e < NV) {
-        const int mm = (2 * e) % M, l = (2 * e) / M;
-        cf z0{buf[it].x * sg, buf[it].y * sg}, z1{buf[it].z * sg, buf[it].w * sg};
-        if constexpr (MODE == PF_BWDH) {
-          if (j0 == 0 && a0 + l == 0 && mm == 0) z0.x -= q;
-        }
-        rows[rpos<M>(l, mm)] = z0;
-        rows[rpos<M>(l, mm + 1)] = z1;
-      }
-    }
-  }
-  if constexpr (MODE != PF_LOADV) {
-    float alpha = 0.0f;
-    if constexpr (MODE == PF_BWDH) alpha = bs->alpha;
-    __syncthreads();
-    for (int qd = t; qd < total; qd += BLOCK) {
-      float4 p0 = pre0, p1 = pre1;
-      if (qd != t) load_rec(sorted, range_pick(R, qd), p0, p1);
-      const uint32_t bb = __float_as_uint(p0.w);
-      const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
-      float val;
-      if constexpr (MODE == PF_BWDH) val = alpha;
-      else val = ch == 0 ? p1.x : (ch == 1 ? p1.y : p1.z);
-#pragma unroll
-      for (int o0 = 0; o0 < 2; ++o0) {
-        if (((b0 + o0) & (RES - 1)) != j0) continue;
-        const float w0 = o0 ? p0.x : 1.0f - p0.x;
-#pragma unroll
-        for (int o1 = 0; o1 < 2; ++o1) {
-          const int l = (b1 + o1 - a0) & (RES - 1);
-          if (l >= RC) continue;
-          const float w01 = w0 * (o1 ? p0.y : 1.0f - p0.y);
-#pragma unroll
-          for (int o2 = 0; o2 < 2; ++o2) {
-            const int nn = (b2 + o2) & (RES - 1);
-            const float w = w01 * (o2 ? p0.z : 1.0f - p0.z);
-            atomicAdd(&rf[2 * rpos<M>(l, nn >> 1) + (nn & 1)], w * val);
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
+  if (MODE == PF_SPLAT && R.total == 0) return false;
+  fill_rows<RES, RC, BLOCK, MODE>(rows, sorted, R, gin, bs, j0, a0, ch);
   {
     cf reg[16];
     fft<M, -1, false, false>(reg, rows + (t / PL::TPR) * LSR, t % PL::TPR, stw, row_swz(M, t / PL::TPR));

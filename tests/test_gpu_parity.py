@@ -103,7 +103,9 @@ def test_spectral_nyquist_and_constant_vanish(psr, dev):
 # ------------------------------------------------------------------ forward
 CASES = [(8, 1, "uniform", 2.0), (8, 9, "uniform", 0.0), (16, 300, "sphere", 2.0), (16, 513, "uniform", 1.0),
          (32, 2049, "torus", 2.0), (64, 4000, "sphere", 3.0), (64, 10007, "uniform", 2.0),
-         (64, 700, "small", 2.0), (128, 3000, "torus", 2.0), (128, 900, "small", 5.0), (256, 1200, "small", 2.0)]
+         (64, 700, "small", 2.0), (128, 3000, "torus", 2.0), (128, 900, "small", 5.0), (256, 1200, "small", 2.0),
+         # spans of more than 65536 points: the splat falls back to float atomics (row and plane passes)
+         (16, 600000, "uniform", 2.0), (64, 2200000, "uniform", 2.0)]
 
 
 @pytest.mark.parametrize("res,P,kind,sigma", CASES)
@@ -134,7 +136,8 @@ def test_forward_c1_sphere(psr, dev):
 @pytest.mark.parametrize("res,P,kind,reading", [(8, 5, "uniform", 0), (16, 300, "torus", 0), (32, 2000, "sphere", 0),
                                                 (32, 1500, "uniform", 1), (64, 6000, "torus", 0),
                                                 (64, 500, "small", 1), (128, 1500, "small", 0),
-                                                (128, 4000, "torus", 1), (256, 800, "small", 0)])
+                                                (128, 4000, "torus", 1), (256, 800, "small", 0),
+                                                (16, 600000, "uniform", 0)])
 def test_backward_matches_oracle(psr, dev, res, P, kind, reading):
     announce(f"backward res={res} P={P} kind={kind} reading={reading}")
     import paper_2106_03452_amd as p
@@ -203,6 +206,12 @@ def test_degenerate_and_nonfinite_status(psr, dev):
     bad[7, 1] = np.nan
     chi, saved = psr.forward(to_dev(bad, dev), to_dev(np.ones((100, 3)), dev), 16, 2.0)
     assert psr.status(saved) == -6 and torch.isnan(chi).all()
+    # a non-finite normal component is reported the same way (row passes and plane passes)
+    for res in (16, 128, 256):
+        nrm = np.ones((100, 3))
+        nrm[3, 2] = np.inf
+        chi, saved = psr.forward(to_dev(pts, dev), to_dev(nrm, dev), res, 2.0)
+        assert psr.status(saved) == -6 and torch.isnan(chi).all()
 
 
 def test_bad_arguments_raise(psr, dev):
@@ -234,9 +243,26 @@ def test_options_m_and_sign_flip(psr, dev):
     assert max_rel(host(chi7), host(chi) * 1.4) < 1e-6
 
 
-def test_repeat_is_stable(psr, dev):
-    sh = S.tiny_case(9, 64, 8000, kind="sphere")
+@pytest.mark.parametrize("res", [32, 64, 256])
+def test_repeat_is_stable(psr, dev, res):
+    # the point order inside a bin may differ between runs (LDS atomics rank
+    # the points); only FP64 sums see it
+    announce(f"repeat res={res}")
+    sh = S.tiny_case(9, res, 8000, kind="sphere")
     pts, nrm = to_dev(sh.points, dev), to_dev(sh.normals, dev)
-    a, _ = psr.forward(pts, nrm, 64, 2.0)
-    b, _ = psr.forward(pts, nrm, 64, 2.0)
-    assert max_rel(host(a), host(b)) < 1e-6
+    G = to_dev(_rng(res).standard_normal((res, res, res)), dev)
+    a, sa = psr.forward(pts, nrm, res, 2.0)
+    b, sb = psr.forward(pts, nrm, res, 2.0)
+    assert max_rel(host(a), host(b)) < 1e-7
+    da = psr.backward(a, sa, G, 8000, res, 2.0)
+    db = psr.backward(b, sb, G, 8000, res, 2.0)
+    assert l2_rel(host(da[0]), host(db[0])) < 1e-7 and l2_rel(host(da[1]), host(db[1])) < 1e-7
+
+
+@pytest.mark.parametrize("res", [16, 64, 256])
+def test_splat_is_bitwise_deterministic(psr, dev, res):
+    # the splat accumulates fixed-point integers: the same bits on every run
+    announce(f"splat bitwise res={res}")
+    sh = S.tiny_case(3 * res, res, 5000, kind="torus")
+    pts, nrm = to_dev(sh.points, dev), to_dev(sh.normals, dev)
+    assert torch.equal(psr.debug_splat(pts, nrm, res), psr.debug_splat(pts, nrm, res))
