@@ -1019,7 +1019,7 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
                                        (float)RES * wa * wb * dL);
           const int slot = o0 * 2 + o1;
           if constexpr (MODE == MODE_FWD) part[s * 4 + slot] = q;
-          else part[(s * 4 + slot) * 3 + c] = q;
+          else part[(s * 3 + c) * 4 + slot] = q;
         }
       }
     });
@@ -1371,7 +1371,7 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
                                         (float)RES * wa * wb * dL);
           const int slot = o0 * 2 + o1;
           if constexpr (MODE == PI_FWD) part[s * 4 + slot] = qv;
-          else part[(s * 4 + slot) * 3 + c] = qv;
+          else part[(s * 3 + c) * 4 + slot] = qv;
         }
       }
     }
@@ -1454,6 +1454,7 @@ __device__ __forceinline__ void b_bwd_reduce(const float* __restrict__ G, const 
   double sg = 0.0, sgc = 0.0;
   const float4* g4 = reinterpret_cast<const float4*>(G);
   const float4* c4 = reinterpret_cast<const float4*>(chi);
+#pragma unroll 4
   for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n / 4; i += (int64_t)nblocks * blockDim.x) {
     const float4 g = g4[i], c = c4[i];
     sg += ((double)g.x + (double)g.y) + ((double)g.z + (double)g.w);
@@ -1503,7 +1504,7 @@ __device__ __forceinline__ void b_bwd_point_finalize(const float4* __restrict__ 
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
 #pragma unroll
     for (int slot = 0; slot < 4; ++slot) {
-      const float4 q = part[(s * 4 + slot) * 3 + c];
+      const float4 q = part[(s * 3 + c) * 4 + slot];
       dn[c] += q.x;
       g0 += q.y;
       g1 += q.z;
