@@ -370,6 +370,61 @@ __device__ __forceinline__ void b_scatter(const PointRec* __restrict__ tmp, cons
 // ---------------------------------------------------------------------------
 enum { MODE_SPLAT = 0, MODE_BWDH = 1, MODE_LOADV = 2, MODE_VOUT = 3 };
 
+// blocks of the grid-stride FP64 reduction over RES^3 / 4 float4 (at least 1)
+template <int RES>
+constexpr int bwd_reduce_blocks() {
+  constexpr int64_t n = ((int64_t)RES * RES * RES / 4 + 255) / 256;
+  return n > kRedBlocks ? kRedBlocks : (int)n;
+}
+
+// The backward's scalars (main Eq. 4 differentiated): Q = sum(G chi) / c,
+// g_mu = -s sum(G) + Q (reading B; A drops Q), alpha = g_mu / P, returned as
+// (s, Q, alpha). Every workgroup of the cotangent pass sums the same FP64
+// per-block partials in the same order; block 0 records them for the final
+// pass. Ends with a barrier.
+template <int BLOCK>
+__device__ __forceinline__ float3 bwd_scalars(const double2* __restrict__ blockpart, int nb,
+                                              const SavedHeader* __restrict__ hdr, BwdScalars* __restrict__ bs,
+                                              bool record) {
+  constexpr int NW = (BLOCK + 63) / 64, W = BLOCK < 64 ? BLOCK : 64;
+  __shared__ double wsum[2][NW];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nb; i += BLOCK) {
+    a += blockpart[i].x;
+    b += blockpart[i].y;
+  }
+#pragma unroll
+  for (int d = W / 2; d > 0; d >>= 1) {
+    a += __shfl_xor(a, d, W);
+    b += __shfl_xor(b, d, W);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    wsum[0][threadIdx.x >> 6] = a;
+    wsum[1][threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
+  double SG = 0.0, SGc = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    SG += wsum[0][w];
+    SGc += wsum[1][w];
+  }
+  const double s = hdr->scale, c = hdr->cscale;
+  const double Q = SGc / c;
+  const double gmu = -s * SG + (hdr->reading == 0 ? Q : 0.0);
+  const float alpha = (float)(gmu / (double)hdr->npoints);
+  if (record && threadIdx.x == 0) {
+    bs->S_G = SG;
+    bs->S_Gchi = SGc;
+    bs->Qd = Q;
+    bs->gmu = gmu;
+    bs->s = (float)s;
+    bs->q = (float)Q;
+    bs->alpha = alpha;
+  }
+  return make_float3((float)s, (float)Q, alpha);
+}
+
 // Rows [a0, a0 + NROWS) of plane j0 of one channel into LDS as float samples
 // (row l, sample n at float slot 2 rpos(l, n/2) + (n & 1)). KIND 0: splat of
 // normal component ch over the points of R; KIND 1: the cotangent
@@ -377,8 +432,7 @@ enum { MODE_SPLAT = 0, MODE_BWDH = 1, MODE_LOADV = 2, MODE_VOUT = 3 };
 // of v_ch from gin. Ends with a barrier.
 template <int RES, int NROWS, int BLOCK, int KIND>
 __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__ sorted, const Ranges& R,
-                                          const float* __restrict__ gin, const BwdScalars* __restrict__ bs, int j0,
-                                          int a0, int ch) {
+                                          const float* __restrict__ gin, float3 sqa, int j0, int a0, int ch) {
   constexpr int M = RES / 2, LS = row_ls(M);
   constexpr int64_t N3 = (int64_t)RES * RES * RES;
   const int t = threadIdx.x;
@@ -464,9 +518,9 @@ __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__
       __syncthreads();
       float sg = 0.0f, q = 0.0f, alpha = 1.0f;
       if constexpr (KIND == 1) {
-        sg = bs->s;
-        q = bs->q;
-        alpha = bs->alpha;
+        sg = sqa.x;
+        q = sqa.y;
+        alpha = sqa.z;
       }
       const float fac = inv * alpha;
 #pragma unroll
@@ -502,7 +556,9 @@ template <int RES, int MODE>
 __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
                                                               const int* __restrict__ off,
                                                               const float* __restrict__ gin,
-                                                              const BwdScalars* __restrict__ bs,
+                                                              BwdScalars* __restrict__ bs,
+                                                              const double2* __restrict__ bpart,
+                                                              const SavedHeader* __restrict__ hdr,
                                                               const cf* __restrict__ tw, cf* __restrict__ out,
                                                               float* __restrict__ vout, int bid) {
   constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_block(RES);
@@ -539,7 +595,9 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
     }
   }
 
-  fill_rows<RES, TR, BR, MODE == MODE_VOUT ? MODE_SPLAT : MODE>(rows, sorted, R, gin, bs, j0, a0, c);
+  float3 sqa = make_float3(1.0f, 0.0f, 1.0f);
+  if constexpr (MODE == MODE_BWDH) sqa = bwd_scalars<BR>(bpart, bwd_reduce_blocks<RES>(), hdr, bs, bid == 0);
+  fill_rows<RES, TR, BR, MODE == MODE_VOUT ? MODE_SPLAT : MODE>(rows, sorted, R, gin, sqa, j0, a0, c);
 
   if constexpr (MODE == MODE_VOUT) {
     for (int e = t; e < TR * RES; e += BR) {
@@ -893,6 +951,7 @@ enum { MODE_FWD = 0, MODE_BWD = 1, MODE_DBG = 2 };
 template <int RES, int MODE>
 __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
                                                                float* __restrict__ chi_out,
+                                                               SavedHeader* __restrict__ hdr,
                                                                const PointRec* __restrict__ sorted,
                                                                const int* __restrict__ off,
                                                                float4* __restrict__ part,
@@ -992,6 +1051,7 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
       const int l = e / M, mm = e % M;
       const cf z = rows[rpos<M>(l, mm)];
       *reinterpret_cast<float2*>(chi_out + ((int64_t)j0 * RES + a0 + l) * RES + 2 * mm) = make_float2(z.x, z.y);
+      if (MODE == MODE_FWD && j0 == 0 && a0 == 0 && e == 0) hdr->chi0 = (double)z.x;  // chi'(0,0,0) for Eq. 4
     }
   }
   if constexpr (MODE != MODE_DBG) {
@@ -1085,14 +1145,14 @@ enum { PF_SPLAT = 0, PF_BWDH = 1, PF_LOADV = 2 };
 template <int RES, int MODE>
 __device__ __forceinline__ bool pf_rows(cf* rows, const cf* stw, const PointRec* __restrict__ sorted,
                                         const int* __restrict__ off, const float* __restrict__ gin,
-                                        const BwdScalars* __restrict__ bs, int j0, int a0, int ch) {
+                                        float3 sqa, int j0, int a0, int ch) {
   using PL = Plane<RES>;
   constexpr int M = PL::M, RC = PL::RC, LSR = PL::LSR, BLOCK = PL::BLOCK;
   const int t = threadIdx.x;
   Ranges R{};
   if constexpr (MODE != PF_LOADV) R = span_ranges<RES, RC>(off, j0, a0);
   if (MODE == PF_SPLAT && R.total == 0) return false;
-  fill_rows<RES, RC, BLOCK, MODE>(rows, sorted, R, gin, bs, j0, a0, ch);
+  fill_rows<RES, RC, BLOCK, MODE>(rows, sorted, R, gin, sqa, j0, a0, ch);
   {
     cf reg[16];
     fft<M, -1, false, false>(reg, rows + (t / PL::TPR) * LSR, t % PL::TPR, stw, row_swz(M, t / PL::TPR));
@@ -1122,7 +1182,8 @@ __device__ __forceinline__ cf pf_pick(const cf* rows, const cf* wr, int l, int k
 // B12 (PF_BWDH): H^ along (j2, j1). Output C[set][j0][k2][k1].
 template <int RES, int MODE>
 __device__ __forceinline__ void b_plane_fwd(const PointRec* __restrict__ sorted, const int* __restrict__ off,
-                                            const float* __restrict__ gin, const BwdScalars* __restrict__ bs,
+                                            const float* __restrict__ gin, BwdScalars* __restrict__ bs,
+                                            const double2* __restrict__ bpart, const SavedHeader* __restrict__ hdr,
                                             const cf* __restrict__ tw, cf* __restrict__ out, int bid) {
   using PL = Plane<RES>;
   constexpr int M = PL::M, H = PL::H, KP = PL::KP, NCOL = PL::NCOL, TPL = PL::TPL, RC = PL::RC;
@@ -1153,6 +1214,8 @@ __device__ __forceinline__ void b_plane_fwd(const PointRec* __restrict__ sorted,
       return;
     }
   }
+  float3 sqa = make_float3(1.0f, 0.0f, 1.0f);
+  if constexpr (MODE == PF_BWDH) sqa = bwd_scalars<BLOCK>(bpart, bwd_reduce_blocks<RES>(), hdr, bs, bid == 0);
   cf reg[16], acc[16];
   const int npass = set == 1 ? 2 : 1;
   for (int pass = 0; pass < npass; ++pass) {
@@ -1160,7 +1223,7 @@ __device__ __forceinline__ void b_plane_fwd(const PointRec* __restrict__ sorted,
 #pragma unroll 1
     for (int q = 0; q < NCHUNK; ++q) {
       const int a0 = q * RC;
-      const bool any = pf_rows<RES, MODE>(buf, stw, sorted, off, gin, bs, j0, a0, ch);
+      const bool any = pf_rows<RES, MODE>(buf, stw, sorted, off, gin, sqa, j0, a0, ch);
 #pragma unroll
       for (int w2 = 0; w2 < VPC; ++w2) {
         const cf x = any ? pf_pick<RES>(buf, ctw, lt + TPL * w2, kk) : cf{0.0f, 0.0f};
@@ -1220,6 +1283,7 @@ enum { PI_FWD = 0, PI_BWD = 1, PI_DBG = 2 };
 // is skipped. Input C[c][j0][k2][k1]; part p owns rows j1 in [p RC, p RC + RC).
 template <int RES, int MODE>
 __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __restrict__ chi_out,
+                                            SavedHeader* __restrict__ hdr,
                                             const PointRec* __restrict__ sorted, const int* __restrict__ off,
                                             float4* __restrict__ part, const cf* __restrict__ tw, int bid) {
   using PL = Plane<RES>;
@@ -1339,6 +1403,7 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
       const int l = e / M, mm = e % M;
       const cf z = buf[rpos<M>(l, mm)];
       *reinterpret_cast<float2*>(chi_out + ((int64_t)j0 * RES + a0 + l) * RES + 2 * mm) = make_float2(z.x, z.y);
+      if (MODE == PI_FWD && j0 == 0 && a0 == 0 && e == 0) hdr->chi0 = (double)z.x;  // chi'(0,0,0) for Eq. 4
     }
   }
   if constexpr (MODE != PI_DBG) {
@@ -1413,29 +1478,37 @@ __device__ __forceinline__ void b_fwd_point_reduce(const float4* __restrict__ pa
 
 // mu = (1/P) sum_i f_i, c = chi'(0) - mu (reading B) or chi'(0) (reading A),
 // s = m/|c| (main Eq. 4), status; block partials summed in a fixed order.
-__device__ __forceinline__ void b_fwd_scalars(const double* __restrict__ blockpart, int nb,
-                                                     const float* __restrict__ chi, SavedHeader* __restrict__ hdr, int bid) {
+// mu, c and s (main Eq. 4) from the per-block FP64 sums of f_i; every caller
+// sums the same partials in the same order, so all agree bit for bit.
+__device__ __forceinline__ void fwd_scalars(const double* __restrict__ blockpart, int nb,
+                                            const SavedHeader* __restrict__ hdr, double& mu, double& scale,
+                                            double& c, int& status) {
   __shared__ double sh[256];
   double a = 0.0;
   for (int i = threadIdx.x; i < nb; i += blockDim.x) a += blockpart[i];
   const double tot = block_sum(a, sh);
-  if (threadIdx.x == 0) {
-    const double mu = tot / (double)hdr->npoints;
-    const double chi0 = (double)chi[0];
-    const double c = hdr->reading == 0 ? chi0 - mu : chi0;
-    int status = 0;
-    if (hdr->flags & 1) status = -6;  // PSR_ENONFINITE
-    else if (!(c != 0.0) || !isfinite(c) || !isfinite(mu)) status = -3;  // PSR_EDEGENERATE
-    hdr->status = status;
-    hdr->mu = mu;
-    hdr->chi0 = chi0;
-    hdr->cscale = c;
-    hdr->scale = status ? __longlong_as_double(0x7ff8000000000000LL) : (double)hdr->m / fabs(c);
-  }
+  mu = tot / (double)hdr->npoints;
+  const double chi0 = hdr->chi0;
+  c = hdr->reading == 0 ? chi0 - mu : chi0;
+  status = 0;
+  if (hdr->flags & 1) status = -6;  // PSR_ENONFINITE
+  else if (!(c != 0.0) || !isfinite(c) || !isfinite(mu)) status = -3;  // PSR_EDEGENERATE
+  scale = status ? __longlong_as_double(0x7ff8000000000000LL) : (double)hdr->m / fabs(c);
 }
 
-__device__ __forceinline__ void b_normalize(float* __restrict__ chi, int64_t n, const SavedHeader* __restrict__ hdr, int bid, int nblocks) {
-  const double mu = hdr->mu, s = hdr->scale;
+// chi = s (chi' - mu) in place; block 0 also records the scalars and the
+// status in the header (chi'(0) was recorded there by the c2r pass).
+__device__ __forceinline__ void b_normalize(float* __restrict__ chi, int64_t n, const double* __restrict__ blockpart,
+                                            int nb, SavedHeader* __restrict__ hdr, int bid, int nblocks) {
+  double mu, s, c;
+  int status;
+  fwd_scalars(blockpart, nb, hdr, mu, s, c, status);
+  if (bid == 0 && threadIdx.x == 0) {
+    hdr->status = status;
+    hdr->mu = mu;
+    hdr->cscale = c;
+    hdr->scale = s;
+  }
   float4* c4 = reinterpret_cast<float4*>(chi);
   for (int64_t i = (int64_t)bid * blockDim.x + threadIdx.x; i < n / 4; i += (int64_t)nblocks * blockDim.x) {
     float4 v = c4[i];
@@ -1466,29 +1539,6 @@ __device__ __forceinline__ void b_bwd_reduce(const float* __restrict__ G, const 
 }
 
 // Q = S_Gchi / c, g_mu = -s S_G + Q (reading B; reading A drops Q), alpha = g_mu / P.
-__device__ __forceinline__ void b_bwd_scalars(const double2* __restrict__ blockpart, int nb,
-                                                     const SavedHeader* __restrict__ hdr, BwdScalars* __restrict__ bs, int bid) {
-  __shared__ double sh[256];
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    a += blockpart[i].x;
-    b += blockpart[i].y;
-  }
-  const double SG = block_sum(a, sh);
-  const double SGc = block_sum(b, sh);
-  if (threadIdx.x == 0) {
-    const double s = hdr->scale, c = hdr->cscale;
-    const double Q = SGc / c;
-    const double gmu = -s * SG + (hdr->reading == 0 ? Q : 0.0);
-    bs->S_G = SG;
-    bs->S_Gchi = SGc;
-    bs->Qd = Q;
-    bs->gmu = gmu;
-    bs->s = (float)s;
-    bs->q = (float)Q;
-    bs->alpha = (float)(gmu / (double)hdr->npoints);
-  }
-}
 
 __device__ __forceinline__ void b_bwd_point_finalize(const float4* __restrict__ part, const float4* __restrict__ gradf,
                                      const PointRec* __restrict__ sorted, const BwdScalars* __restrict__ bs,
@@ -1589,7 +1639,8 @@ template <int RES, int MODE, int MAXJ>
 __global__ __launch_bounds__(rows_block(RES)) void k_splat_r2c(const Batch<MAXJ> B) {
   PSR_JOB(RES);
   const float* gin = MODE == MODE_BWDH ? J.dchi : J.aux_in;
-  b_splat_r2c<RES, MODE>(sv.sorted, sv.off, gin, w.bs, B.tw, w.X, J.aux_out, bid);
+  b_splat_r2c<RES, MODE>(sv.sorted, sv.off, gin, w.bs, (const double2*)w.blockpart, sv.hdr, B.tw, w.X, J.aux_out,
+                         bid);
 }
 
 template <int RES, bool MERGE, bool SKIP, int MAXJ>
@@ -1620,7 +1671,7 @@ template <int RES, int MODE, int MAXJ>
 __global__ __launch_bounds__(rows_block(RES)) void k_c2r_gather(const Batch<MAXJ> B) {
   PSR_JOB(RES);
   float* out = MODE == MODE_DBG ? J.aux_out : J.chi;
-  b_c2r_gather<RES, MODE>(w.Y, out, sv.sorted, sv.off, w.part, B.tw, bid);
+  b_c2r_gather<RES, MODE>(w.Y, out, sv.hdr, sv.sorted, sv.off, w.part, B.tw, bid);
 }
 
 template <int RES, int MODE, int MAXJ>
@@ -1628,7 +1679,7 @@ __global__ __launch_bounds__(Plane<RES>::BLOCK) __attribute__((amdgpu_waves_per_
 void k_plane_fwd(const Batch<MAXJ> B) {
   PSR_JOB(RES);
   const float* gin = MODE == PF_BWDH ? J.dchi : J.aux_in;
-  b_plane_fwd<RES, MODE>(sv.sorted, sv.off, gin, w.bs, B.tw, w.Y, bid);
+  b_plane_fwd<RES, MODE>(sv.sorted, sv.off, gin, w.bs, (const double2*)w.blockpart, sv.hdr, B.tw, w.Y, bid);
 }
 
 template <int RES, int MODE, int MAXJ>
@@ -1636,7 +1687,7 @@ __global__ __launch_bounds__(Plane<RES>::BLOCK) __attribute__((amdgpu_waves_per_
 void k_plane_inv(const Batch<MAXJ> B) {
   PSR_JOB(RES);
   float* outp = MODE == PI_DBG ? J.aux_out : J.chi;
-  b_plane_inv<RES, MODE>(w.X, outp, sv.sorted, sv.off, w.part, B.tw, bid);
+  b_plane_inv<RES, MODE>(w.X, outp, sv.hdr, sv.sorted, sv.off, w.part, B.tw, bid);
 }
 
 template <int RES, int MAXJ>
@@ -1646,16 +1697,10 @@ __global__ __launch_bounds__(256) void k_fwd_point_reduce(const Batch<MAXJ> B) {
 }
 
 template <int RES, int MAXJ>
-__global__ __launch_bounds__(256) void k_fwd_scalars(const Batch<MAXJ> B) {
-  PSR_JOB(RES);
-  const int nb = (int)((J.P + 255) / 256) > kRedBlocks ? kRedBlocks : (int)((J.P + 255) / 256);
-  b_fwd_scalars(w.blockpart, nb, J.chi, sv.hdr, bid);
-}
-
-template <int RES, int MAXJ>
 __global__ __launch_bounds__(256) void k_normalize(const Batch<MAXJ> B) {
   PSR_JOB(RES);
-  b_normalize(J.chi, (int64_t)RES * RES * RES, sv.hdr, bid, nbl);
+  const int nb = (int)((J.P + 255) / 256) > kRedBlocks ? kRedBlocks : (int)((J.P + 255) / 256);
+  b_normalize(J.chi, (int64_t)RES * RES * RES, w.blockpart, nb, sv.hdr, bid, nbl);
 }
 
 template <int RES, int MAXJ>
@@ -1664,18 +1709,7 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(const Batch<MAXJ> B) {
   b_bwd_reduce(J.dchi, J.chi, (int64_t)RES * RES * RES, (double2*)w.blockpart, bid, nbl);
 }
 
-// blocks of the grid-stride FP64 reduction over RES^3 / 4 float4 (at least 1)
-template <int RES>
-constexpr int bwd_reduce_blocks() {
-  constexpr int64_t n = ((int64_t)RES * RES * RES / 4 + 255) / 256;
-  return n > kRedBlocks ? kRedBlocks : (int)n;
-}
 
-template <int RES, int MAXJ>
-__global__ __launch_bounds__(256) void k_bwd_scalars(const Batch<MAXJ> B) {
-  PSR_JOB(RES);
-  b_bwd_scalars((const double2*)w.blockpart, bwd_reduce_blocks<RES>(), sv.hdr, w.bs, bid);
-}
 
 template <int RES, int MAXJ>
 __global__ __launch_bounds__(256) void k_bwd_point_finalize(const Batch<MAXJ> B) {
@@ -1699,7 +1733,7 @@ struct Grid {
   static constexpr int BR = rows_block(RES), BC = cols_block(RES);
   static constexpr int64_t N3 = (int64_t)RES * RES * RES;
   static constexpr int init_blocks = nblk_c(num_bins(RES), 256) > 64 ? 64 : nblk_c(num_bins(RES), 256);
-  static constexpr int norm_blocks = nblk_c(N3 / 4, 256) > 4096 ? 4096 : nblk_c(N3 / 4, 256);
+  static constexpr int norm_blocks = nblk_c(N3 / 4, 256) > 1024 ? 1024 : nblk_c(N3 / 4, 256);
 };
 
 // Launch kernel K once per chunk of up to MAXJ jobs; workgroups per job from nb(job).
@@ -1766,7 +1800,6 @@ static int seq_forward(Exec& x, const JobArg* J, int n) {
   x.begin(STAGE_FWD_REDUCE);
   rc |= launch<MAXJ>(x, k_fwd_point_reduce<RES, MAXJ>, 256, J, n,
                      [](const JobArg& a) { return nblk(a.P, 256) > kRedBlocks ? kRedBlocks : nblk(a.P, 256); });
-  rc |= launch<MAXJ>(x, k_fwd_scalars<RES, MAXJ>, 256, J, n, c(1));
   x.end(STAGE_FWD_REDUCE);
   x.begin(STAGE_NORMALIZE);
   rc |= launch<MAXJ>(x, k_normalize<RES, MAXJ>, 256, J, n, c(G::norm_blocks));
@@ -1781,7 +1814,6 @@ static int seq_backward(Exec& x, const JobArg* J, int n) {
   auto c = [](int v) { return [v](const JobArg&) { return v; }; };
   x.begin(STAGE_BWD_REDUCE);
   rc |= launch<MAXJ>(x, k_bwd_reduce<RES, MAXJ>, 256, J, n, c(bwd_reduce_blocks<RES>()));
-  rc |= launch<MAXJ>(x, k_bwd_scalars<RES, MAXJ>, 256, J, n, c(1));
   x.end(STAGE_BWD_REDUCE);
   if constexpr (use_plane(RES)) {
     x.begin(STAGE_B12);
