@@ -12,13 +12,18 @@
 //   P5       complex-to-real inverse FFT along j2, write chi', and the
 //            trilinear gather of chi' at the points (value + gradient)
 //   reduce   FP64 mean at the points, scale c (main Eq. 4), normalise chi
+// At 64^3 and 128^3 the plane passes P12 (= P1 + P2) and P45 (= P4 + P5) run
+// two axes per kernel with a whole j0 plane on chip; at 256^3 only P45 does.
 // The backward runs the adjoint of every step (FP64 sums of G and G*chi, the
-// cotangent H, conjugate operator, 3 inverse channels, gather of dL/dv).
+// cotangent H, conjugate operator, 3 inverse channels, gather of dL/dv), with
+// the same pass structure (B1..B5, B12, B45). Planes and row tiles that no
+// point reaches are skipped where their values are zero or unused. The splat
+// accumulates fixed-point integers in LDS (bitwise reproducible).
 //
 // Layouts (complex64 unless noted; H = r/2 + 1 half-spectrum planes):
 //   A[c][k2][j0][j1]   P1 out, P2 in   (3 channels fwd, 1 bwd)
 //   B[c][k1][k2][j0]   P2 out, P3 in   (2 fwd, 1 bwd)
-//   C[c][j0][k2][k1]   P3 out, P4 in   (1 fwd, 2 bwd)
+//   C[c][j0][k2][k1]   P3 out, P4/P45 in (1 fwd, 2 bwd); P12 out, P3 in
 //   D[c][k2][j0][j1]   P4 out, P5 in   (1 fwd, 3 bwd)
 // Each pass reads whole contiguous lines or multi-line segments and writes
 // the other, so every global access is at least a 128-byte run. FFT data
