@@ -31,7 +31,7 @@ def _mixed_jobs(dev, n, seed, with_bwd=True, res_choices=(16, 32, 64)):
     return jobs, shapes
 
 
-@pytest.mark.parametrize("n,res_choices", [(30, (16, 32, 64)), (29, (32,))])
+@pytest.mark.parametrize("n,res_choices", [(30, (16, 32, 64)), (29, (32,)), (12, (64, 128)), (3, (256,))])
 def test_batch_equals_solo(dev, n, res_choices):
     announce(f"batch of {n} jobs res {res_choices} vs solo")
     from paper_2106_03452_amd import function as F
