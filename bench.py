@@ -212,12 +212,14 @@ import numpy as np
 import oracle, psr_synth as S
 sh = S.config_c3()
 chi_t, _ = oracle.forward(sh.points_clean, sh.normals_clean, sh.res, sh.sigma)
-t0 = time.perf_counter()
-chi, aux = oracle.forward(sh.points, sh.normals, sh.res, sh.sigma)
-G = 2.0 * (chi - chi_t) / chi.size
-dc, dn = oracle.backward(aux, G)
-t1 = time.perf_counter()
-print(json.dumps(dict(seconds=t1 - t0)))
+secs = []
+for _ in range(3):
+    t0 = time.perf_counter()
+    chi, aux = oracle.forward(sh.points, sh.normals, sh.res, sh.sigma)
+    G = 2.0 * (chi - chi_t) / chi.size
+    dc, dn = oracle.backward(aux, G)
+    secs.append(time.perf_counter() - t0)
+print(json.dumps(dict(seconds=sorted(secs)[1])))
 """
 
 
@@ -231,9 +233,26 @@ def cpu_baseline():
         return None
     sec = json.loads(out.stdout.strip().splitlines()[-1])["seconds"]
     return {"value": round(1.0 / sec, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full forward+backward solve of the same 256^3 / 100k-point workload "
-                      f"(FP64 NumPy oracle, single thread, {sec:.1f} s; loss target chi_t computed "
-                      f"outside the timed sample)"}
+            "sample": f"three full forward+backward solves of the same 256^3 / 100k-point workload, median "
+                      f"{sec:.1f} s (FP64 NumPy oracle, single thread; the loss target chi_t is computed "
+                      f"outside the timed samples)"}
+
+
+def step_times(step, reps, torch, scrub=None):
+    """Per-repetition durations (ms) of one step from HIP events on the current
+    stream; with scrub, a 512 MiB device write runs before each repetition
+    (outside the events) so the step starts with cold caches."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        if scrub is not None:
+            scrub.fill_(1.0)
+        a.record()
+        step()
+        b.record()
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) for a, b in ev)
+    q = lambda f: round(t[min(len(t) - 1, int(f * len(t)))], 4)
+    return {"median_ms": q(0.5), "p10_ms": q(0.1), "p90_ms": q(0.9), "reps": reps}
 
 
 # --------------------------------------------------------------------------- GPU runs
@@ -468,6 +487,15 @@ def main():
                  "frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                  "model": "B_stage = 128 r^3 + 72 P (fwd+bwd)"}
     breakdown = {k: round(v, 4) for k, v in sorted(per_launch.items(), key=lambda kv: -kv[1])}
+    step_roof["B_min"] = 56 * r ** 3 + 72 * P
+    step_roof["B_min_frac"] = round(step_roof["B_min"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    tr = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic_c3_256.json"))) if traffic is not None else None
+    if tr is not None:
+        step_roof["counter_bytes_large_kernels"] = sum(v["hbm_bytes_per_launch"] for v in tr["stages"].values())
+    # warm (back-to-back) and cold (caches scrubbed by a 512 MiB write) repetitions
+    scrub = torch.empty(1 << 27, dtype=torch.float32, device=dev)
+    timing = {"warm": step_times(step, 50, torch), "cold": step_times(step, 50, torch, scrub)}
+    del scrub
 
     secondary = {}
     if not args.no_secondary:
@@ -480,9 +508,13 @@ def main():
         s2 = make_step(b2, ctx)
         d2 = timed(s2, args.steps * 3, args.warmup, torch)
         ms2 = d2 / (args.steps * 3) * 1e3
+        scrub = torch.empty(1 << 27, dtype=torch.float32, device=dev)
         secondary["fwd_bwd_128"] = {"solves_per_s": round(args.steps * 3 / d2, 2), "ms": round(ms2, 4),
                                     "step_roofline_frac": round(b_stage(128, sh2.P) / (ms2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                    "workload": "128^3, 20k points torus+sphere, sigma 2"}
+                                    "workload": "128^3, 20k points torus+sphere, sigma 2",
+                                    "step_timing_200": {"warm": step_times(s2, 200, torch),
+                                                        "cold": step_times(s2, 200, torch, scrub)}}
+        del scrub
         f2 = make_step(b2, ctx, backward=False)
         d3 = timed(f2, args.steps * 3, 2, torch)
         secondary["fwd_only_128"] = {"solves_per_s": round(args.steps * 3 / d3, 2),
@@ -498,7 +530,7 @@ def main():
         "config": {"workload": "fwd+bwd 256^3, 100k points on a superellipsoid (seed 2), noisy normals, sigma 2",
                    "res": r, "npoints": P, "sigma": shape.sigma, "precision": "FP32 grid, FP64 reductions",
                    "parallelism": "single GPU"},
-        "roofline": roof, "step_roofline": step_roof, "stage_ms": breakdown,
+        "roofline": roof, "step_roofline": step_roof, "step_timing_50": timing, "stage_ms": breakdown,
         "dominant_kernel_region_ms_per_step": round(dt2 / args.steps * 1e3, 4),
         "secondary": secondary, "cpu_baseline": cpu,
     }
