@@ -33,6 +33,7 @@ struct SavedHeader {
   double cscale;    // c (reading B: chi'(0) - mu; reading A: chi'(0))
   double scale;     // m / |c|
   double chi0;      // chi'(0,0,0)
+  uint32_t live[16];  // bit j0: some point's corners reach plane j0 (j0 < 512)
 };
 
 // Backward scalars computed on the device from the FP64 reductions.

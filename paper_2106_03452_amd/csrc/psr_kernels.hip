@@ -358,6 +358,44 @@ __device__ __forceinline__ void b_scan(const int* __restrict__ counts, int* __re
   if (t == 0) off[n] = carry;
 }
 
+// Bitmap of the planes some point's corners reach (floor planes j0 - 1 and
+// j0 hold points), from the finished bin offsets; one workgroup.
+template <int RES>
+__device__ __forceinline__ void b_live_planes(const int* __restrict__ off, SavedHeader* __restrict__ hdr) {
+  constexpr int NB = 2 * row_tiles(RES);  // bins per floor plane
+  __shared__ uint32_t bits[16];
+  const int t = threadIdx.x;
+  if (t < 16) bits[t] = 0;
+  __syncthreads();  // also orders this workgroup's offset writes before the reads below
+  for (int j0 = t; j0 < RES; j0 += blockDim.x) {
+    const int jm = (j0 - 1) & (RES - 1);
+    if ((off[j0 * NB + NB] - off[j0 * NB]) + (off[jm * NB + NB] - off[jm * NB]) > 0)
+      atomicOr(&bits[j0 >> 5], 1u << (j0 & 31));
+  }
+  __syncthreads();
+  if (t < 16) hdr->live[t] = bits[t];
+}
+
+__device__ __forceinline__ bool live_bit(const uint32_t* live, int j0) { return (live[j0 >> 5] >> (j0 & 31)) & 1u; }
+
+// The plane bitmap held in registers (uniform loads), for per-element tests
+// that should not wait on a dependent load.
+template <int RES>
+struct LiveBits {
+  uint32_t w[(RES + 31) / 32];
+  __device__ __forceinline__ void load(const uint32_t* __restrict__ p) {
+#pragma unroll
+    for (int k = 0; k < (RES + 31) / 32; ++k) w[k] = p[k];
+  }
+  __device__ __forceinline__ bool operator()(int j0) const {
+    uint32_t x = w[0];
+#pragma unroll
+    for (int k = 1; k < (RES + 31) / 32; ++k)
+      if ((j0 >> 5) == k) x = w[k];
+    return (x >> (j0 & 31)) & 1u;
+  }
+};
+
 __device__ __forceinline__ void b_scatter(const PointRec* __restrict__ tmp, const int2* __restrict__ colrank,
                           const int* __restrict__ off, PointRec* __restrict__ sorted, int64_t npoints, int bid) {
   const int64_t i = (int64_t)bid * blockDim.x + threadIdx.x;
@@ -669,11 +707,13 @@ __device__ __forceinline__ void load_transposed(cf* rows, const cf* __restrict__
 }
 
 // Store the canonical registers of TC lines transposed: out[n][a0 + l] for
-// every element n of every line l, two lines per 16-byte store; with a mask,
-// only the elements n with keep[n] != 0.
+// every element n of every line l, two lines per 16-byte store; with masks,
+// only the elements n with keep[n] != 0 and the line pairs with a line whose
+// keep_line is set.
 template <int RES, int TC = tile_cols(RES)>
 __device__ __forceinline__ void store_transposed(cf* rows, const cf* reg, cf* __restrict__ dst, int64_t stride_n,
-                                                 int l, int lt, const int* keep = nullptr) {
+                                                 int l, int lt, const int* keep = nullptr,
+                                                 const int* keep_line = nullptr) {
   constexpr int BC = TC * plan_TPL(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
 #pragma unroll
   for (int v = 0; v < E; ++v) rows[l * LS + pidx(lt + TPL * v)] = reg[v];
@@ -681,6 +721,7 @@ __device__ __forceinline__ void store_transposed(cf* rows, const cf* reg, cf* __
   for (int e = threadIdx.x; e < RES * (TC / 2); e += BC) {
     const int l2 = 2 * (e % (TC / 2)), n = e / (TC / 2);
     if (keep && !keep[n]) continue;
+    if (keep_line && !keep_line[l2] && !keep_line[l2 + 1]) continue;
     const cf x0 = rows[l2 * LS + pidx(n)], x1 = rows[(l2 + 1) * LS + pidx(n)];
     *reinterpret_cast<float4*>(dst + n * stride_n + l2) = make_float4(x0.x, x0.y, x1.x, x1.y);
   }
@@ -695,7 +736,8 @@ __device__ __forceinline__ void store_transposed(cf* rows, const cf* reg, cf* __
 // ---------------------------------------------------------------------------
 template <int RES, bool MERGE, bool SKIP>
 __device__ __forceinline__ void b_axis1_fwd(const cf* __restrict__ in, cf* __restrict__ out,
-                                            const cf* __restrict__ tw, const int* __restrict__ off, int bid) {
+                                            const cf* __restrict__ tw, const uint32_t* __restrict__ livebits,
+                                            int bid) {
   constexpr int H = RES / 2 + 1, TC = tile_cols(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
   constexpr int64_t CH = (int64_t)H * RES * RES;  // elements per channel
   __shared__ cf rows[TC * LS];
@@ -709,8 +751,11 @@ __device__ __forceinline__ void b_axis1_fwd(const cf* __restrict__ in, cf* __res
   const int a0 = tb * TC;
   const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
   const cf* src = in + ((int64_t)k2 * RES + a0 + l) * RES;
-  // SKIP: lines of a plane no point reaches were never written; they are zero
-  const bool live = !SKIP || plane_live<RES>(off, a0 + l);
+  // SKIP: lines of a plane no point reaches were never written; they are zero,
+  // and P3 does not read their transforms either
+  __shared__ int line_live[SKIP ? TC : 1];
+  const bool live = !SKIP || live_bit(livebits, a0 + l);
+  if (SKIP && lt == 0) line_live[l] = live;
   cf reg[E];
   if (!MERGE || c == 0) {
 #pragma unroll
@@ -734,7 +779,8 @@ __device__ __forceinline__ void b_axis1_fwd(const cf* __restrict__ in, cf* __res
       reg[v] = cf{acc[v].x + k1f * reg[v].x, acc[v].y + k1f * reg[v].y};
     }
   }
-  store_transposed<RES>(rows, reg, out + ((int64_t)c * RES * H + k2) * RES + a0, (int64_t)H * RES, l, lt);
+  store_transposed<RES>(rows, reg, out + ((int64_t)c * RES * H + k2) * RES + a0, (int64_t)H * RES, l, lt, nullptr,
+                        SKIP ? line_live : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -764,9 +810,10 @@ __device__ __forceinline__ float spectral_F(const float* g1, int k0, float g12, 
   return K2 == 0.0f ? 0.0f : g1[k0] * g12 * c / K2;
 }
 
-template <int RES, bool IN_C>
+template <int RES, bool IN_C, bool SKIP>
 __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __restrict__ out,
-                                                               const cf* __restrict__ tw, float sigma, int bid) {
+                                            const cf* __restrict__ tw, float sigma,
+                                            const uint32_t* __restrict__ livebits, int bid) {
   constexpr int H = RES / 2 + 1, TC = tile_j0(RES), TPL = plan_TPL(RES), E = plan_E(RES), LS = lstride(RES);
   __shared__ cf rows[TC * LS];
   __shared__ cf stw[RES];
@@ -781,6 +828,8 @@ __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __res
   constexpr int64_t CH = (int64_t)H * RES * RES;
   cf acc[E], reg[E];
   // sum_d kappa_d v~_d = kappa_0(k0) FFT_j0(v~_0) + FFT_j0(W)
+  // SKIP (two-pass path): elements j0 of planes no point reaches are zero and
+  // were not written by P2
   if constexpr (IN_C) {
     const cf* src = in + (int64_t)k2 * RES + a0;  // element j0 of line k1 at src[j0 H RES + l]
     load_transposed<RES, TC>(rows, src, (int64_t)H * RES);
@@ -792,10 +841,14 @@ __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __res
   } else {
     const cf* src = in + ((int64_t)k1 * H + k2) * RES;
     cf nxt[E];  // W's line is loaded under the first transform
+    LiveBits<RES> lb;
+    if constexpr (SKIP) lb.load(livebits);
 #pragma unroll
-    for (int v = 0; v < E; ++v) reg[v] = src[lt + TPL * v];
-#pragma unroll
-    for (int v = 0; v < E; ++v) nxt[v] = src[CH + lt + TPL * v];
+    for (int v = 0; v < E; ++v) {
+      const bool lv = !SKIP || lb(lt + TPL * v);
+      reg[v] = lv ? src[lt + TPL * v] : cf{0.0f, 0.0f};
+      nxt[v] = lv ? src[CH + lt + TPL * v] : cf{0.0f, 0.0f};
+    }
     fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
 #pragma unroll
     for (int v = 0; v < E; ++v) {
@@ -1207,10 +1260,10 @@ __device__ __forceinline__ void b_plane_fwd(const PointRec* __restrict__ sorted,
   const int t = threadIdx.x, col = t / TPL, lt = t % TPL;
   const int kk = part * NCOL + col;  // packed column index; 0 = (k2 = 0, k2 = M)
   cf* const o = out + set * CH + (int64_t)j0 * H * RES;
-  const int nout = NCOL + (part == 0 ? 1 : 0);  // output k2 columns of this part (part 0 adds k2 = M)
   if constexpr (MODE == PF_SPLAT) {
     // no point touches the plane: its spectrum is zero
     if (span_ranges<RES, RES>(off, j0, 0).total == 0) {
+      const int nout = NCOL + (part == 0 ? 1 : 0);  // output k2 columns of this part (part 0 adds k2 = M)
       for (int e = t; e < nout * (RES / 2); e += BLOCK) {
         const int i = e / (RES / 2), k1 = 2 * (e % (RES / 2));
         const int k2 = i == NCOL ? M : part * NCOL + i;
@@ -1632,6 +1685,7 @@ template <int RES, int MAXJ>
 __global__ __launch_bounds__(1024) void k_scan(const Batch<MAXJ> B) {
   PSR_JOB(RES);
   b_scan(w.counts, sv.off, num_bins(RES), bid);
+  b_live_planes<RES>(sv.off, sv.hdr);
 }
 
 template <int RES, int MAXJ>
@@ -1651,13 +1705,14 @@ __global__ __launch_bounds__(rows_block(RES)) void k_splat_r2c(const Batch<MAXJ>
 template <int RES, bool MERGE, bool SKIP, int MAXJ>
 __global__ __launch_bounds__(cols_block(RES)) void k_axis1_fwd(const Batch<MAXJ> B) {
   PSR_JOB(RES);
-  b_axis1_fwd<RES, MERGE, SKIP>(w.X, w.Y, B.tw, sv.off, bid);
+  b_axis1_fwd<RES, MERGE, SKIP>(w.X, w.Y, B.tw, sv.hdr->live, bid);
 }
 
-template <int RES, int MAXJ>
+template <int RES, bool SKIP, int MAXJ>
 __global__ __launch_bounds__(j0_block(RES)) void k_fwd_axis0(const Batch<MAXJ> B) {
   PSR_JOB(RES);
-  b_fwd_axis0<RES, use_plane(RES)>(w.Y, w.X, B.tw, J.sigma, bid);
+  constexpr bool SK = SKIP && !use_plane(RES);
+  b_fwd_axis0<RES, use_plane(RES), SK>(w.Y, w.X, B.tw, J.sigma, SK ? sv.hdr->live : nullptr, bid);
 }
 
 template <int RES, int MAXJ>
@@ -1788,7 +1843,7 @@ static int seq_forward(Exec& x, const JobArg* J, int n) {
     x.end(STAGE_P2);
   }
   x.begin(STAGE_P3);
-  rc |= launch<MAXJ>(x, k_fwd_axis0<RES, MAXJ>, G::BJ, J, n, c(G::j0s));
+  rc |= launch<MAXJ>(x, k_fwd_axis0<RES, true, MAXJ>, G::BJ, J, n, c(G::j0s));
   x.end(STAGE_P3);
   if constexpr (use_plane_p45(RES)) {
     x.begin(STAGE_P45);
@@ -1876,7 +1931,7 @@ static int debug_spectral_res(Exec& x, const JobArg& job) {
     rc |= launch<1>(x, k_splat_r2c<RES, MODE_LOADV, 1>, G::BR, &job, 1, c(3 * G::rows));
     rc |= launch<1>(x, k_axis1_fwd<RES, true, false, 1>, G::BC, &job, 1, c(2 * G::cols));
   }
-  rc |= launch<1>(x, k_fwd_axis0<RES, 1>, G::BJ, &job, 1, c(G::j0s));
+  rc |= launch<1>(x, k_fwd_axis0<RES, false, 1>, G::BJ, &job, 1, c(G::j0s));
   if constexpr (use_plane_p45(RES)) {
     rc |= launch<1>(x, k_plane_inv<RES, PI_DBG, 1>, Plane<RES>::BLOCK, &job, 1, c(RES * Plane<RES>::KP));
   } else {
