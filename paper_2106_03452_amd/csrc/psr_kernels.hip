@@ -483,8 +483,11 @@ __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__
   // the NROWS rows are one contiguous run of NROWS * RES floats
   constexpr int NV = NROWS * M / 2;  // float4 = two complex slots
   constexpr int IT = (NV + BLOCK - 1) / BLOCK;
-  if constexpr (KIND == 2) {
-    const float4* g4 = reinterpret_cast<const float4*>(gin + ch * N3 + ((int64_t)j0 * RES + a0) * RES);
+  if (KIND == 2 || (KIND == 1 && R.total == 0)) {
+    // rows straight from memory: v_ch (KIND 2), or s G - Q delta_0 where no
+    // point adds to W (KIND 1; uniform over the workgroup)
+    const float sg = KIND == 1 ? sqa.x : 1.0f;
+    const float4* g4 = reinterpret_cast<const float4*>(gin + (KIND == 2 ? ch * N3 : 0) + ((int64_t)j0 * RES + a0) * RES);
     float4 buf[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -496,11 +499,13 @@ __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__
       const int e = t + it * BLOCK;
       if (e < NV) {
         const int mm = (2 * e) % M, l = (2 * e) / M;
-        rows[rpos<M>(l, mm)] = cf{buf[it].x, buf[it].y};
-        rows[rpos<M>(l, mm + 1)] = cf{buf[it].z, buf[it].w};
+        cf z0{buf[it].x * sg, buf[it].y * sg};
+        if (KIND == 1 && j0 == 0 && a0 + l == 0 && mm == 0) z0.x -= sqa.y;
+        rows[rpos<M>(l, mm)] = z0;
+        rows[rpos<M>(l, mm + 1)] = cf{buf[it].z * sg, buf[it].w * sg};
       }
     }
-  } else {
+  } else if constexpr (KIND != 2) {
     // splat of normal component ch (or of unit weights: W in the backward),
     // in fixed point unless the span is very dense; then back to floats, and
     // in the backward H = s G - Q delta_0 + alpha W
