@@ -182,8 +182,9 @@ __device__ __forceinline__ void for_recs(const Recs<K>& r, const PointRec* __res
 // at most |value| to a vertex, once, so every partial sum stays below
 // 2^30 + T / 2 < 2^31; the step 2^-S is below 2 T maxabs / 2^30. Integer sums
 // do not depend on the order of the adds: the splat is bitwise reproducible.
-// Spans of more than kFixedMaxPoints points (where that step would approach
-// the FP32 rounding of the values) keep LDS float atomics.
+// Spans of more than kFixedMaxPoints points, where one point's contribution
+// would be resolved to fewer than 2^30 / T = 2^14 steps of maxabs, keep LDS
+// float atomics.
 constexpr int kFixedMaxPoints = 1 << 16;
 
 // Returns 2^S for T = cnt points bounded by maxabs and sets inv = 2^-S (both
@@ -1004,7 +1005,10 @@ __device__ __forceinline__ void b_axis1_inv(const cf* __restrict__ in, cf* __res
 // P5 / B5: complex-to-real inverse FFT along k2 of a row tile of one channel,
 // then the trilinear gather at the points whose corner lines fall in the tile.
 // Per (point, corner line, channel) the partial is (value, d/dc0, d/dc1,
-// d/dc2) of the interpolant restricted to that line.
+// d/dc2) of the interpolant restricted to that line. Partials are slot-major,
+// one array of np float4 per (channel, corner line): part[(c 4 + slot) np + s]
+// with slot = 2 o0 + o1, so the lanes of a wavefront, which hold consecutive
+// sorted points, store whole lines.
 // MODE_FWD: chi' (1 channel): writes chi' rows and the partials.
 // MODE_BWD: g_v channel c (grid x3): partials only.
 // MODE_DBG: chi' rows only.
@@ -1017,7 +1021,7 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
                                                                SavedHeader* __restrict__ hdr,
                                                                const PointRec* __restrict__ sorted,
                                                                const int* __restrict__ off,
-                                                               float4* __restrict__ part,
+                                                               float4* __restrict__ part, int64_t np,
                                                                const cf* __restrict__ tw, int bid) {
   constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_block(RES);
   constexpr int TPL = plan_TPL(M), E = plan_E(M), LS = row_ls(M);
@@ -1141,8 +1145,7 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
           const float4 q = make_float4(wa * wb * L, (float)RES * sa * wb * L, (float)RES * wa * sb * L,
                                        (float)RES * wa * wb * dL);
           const int slot = o0 * 2 + o1;
-          if constexpr (MODE == MODE_FWD) part[s * 4 + slot] = q;
-          else part[(s * 3 + c) * 4 + slot] = q;
+          part[((MODE == MODE_FWD ? 0 : c * 4) + slot) * np + s] = q;
         }
       }
     });
@@ -1340,7 +1343,8 @@ __device__ __forceinline__ void b_plane_fwd(const PointRec* __restrict__ sorted,
 
 enum { PI_FWD = 0, PI_BWD = 1, PI_DBG = 2 };
 
-// P45 (PI_FWD): chi' rows and the gather partials at the points; PI_DBG:
+// P45 (PI_FWD): chi' rows and the gather partials at the points (slot-major,
+// as in P5 / B5); PI_DBG:
 // chi' rows only. B45 (PI_BWD, grid x3): g_v channel c = IFFT of V0, of
 // kappa_1 U and of kappa_2 U, gather partials only; a part no point touches
 // is skipped. Input C[c][j0][k2][k1]; part p owns rows j1 in [p RC, p RC + RC).
@@ -1348,7 +1352,8 @@ template <int RES, int MODE>
 __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __restrict__ chi_out,
                                             SavedHeader* __restrict__ hdr,
                                             const PointRec* __restrict__ sorted, const int* __restrict__ off,
-                                            float4* __restrict__ part, const cf* __restrict__ tw, int bid) {
+                                            float4* __restrict__ part, int64_t np, const cf* __restrict__ tw,
+                                            int bid) {
   using PL = Plane<RES>;
   constexpr int M = PL::M, H = PL::H, KP = PL::KP, NCOL = PL::NCOL, TPL = PL::TPL, RC = PL::RC;
   constexpr int LSR = PL::LSR, LSC = PL::LSC, BLOCK = PL::BLOCK, TPR = PL::TPR;
@@ -1370,14 +1375,6 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
   if constexpr (MODE != PI_DBG) R = span_ranges<RES, RC>(off, j0, a0);
   const int total = R.total;
   if (MODE == PI_BWD && total == 0) return;
-  float4 pre0 = make_float4(0, 0, 0, 0), pre1 = pre0;
-  int64_t pre_s = 0;
-  if constexpr (MODE != PI_DBG) {
-    if (t < total) {
-      pre_s = range_pick(R, t);
-      load_rec(sorted, pre_s, pre0, pre1);
-    }
-  }
   const cf* const src = in + (MODE == PI_BWD && c > 0 ? CH : 0) + (int64_t)j0 * H * RES;
   cf keep[KP][VK];
 #pragma unroll
@@ -1428,6 +1425,15 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
       } else {
         buf[rpos<M>(l, kk)] = keep[rd][w2];
       }
+    }
+  }
+  // the first gather record of each thread, in flight during the row phase
+  float4 pre0 = make_float4(0, 0, 0, 0), pre1 = pre0;
+  int64_t pre_s = 0;
+  if constexpr (MODE != PI_DBG) {
+    if (t < total) {
+      pre_s = range_pick(R, t);
+      load_rec(sorted, pre_s, pre0, pre1);
     }
   }
   __syncthreads();
@@ -1498,8 +1504,7 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
           const float4 qv = make_float4(wa * wb * L, (float)RES * sa * wb * L, (float)RES * wa * sb * L,
                                         (float)RES * wa * wb * dL);
           const int slot = o0 * 2 + o1;
-          if constexpr (MODE == PI_FWD) part[s * 4 + slot] = qv;
-          else part[(s * 3 + c) * 4 + slot] = qv;
+          part[((MODE == PI_FWD ? 0 : c * 4) + slot) * np + s] = qv;
         }
       }
     }
@@ -1529,7 +1534,7 @@ __device__ __forceinline__ void b_fwd_point_reduce(const float4* __restrict__ pa
   __shared__ double sh[256];
   double acc = 0.0;
   for (int64_t s = (int64_t)bid * blockDim.x + threadIdx.x; s < npoints; s += (int64_t)nblocks * blockDim.x) {
-    const float4 q0 = part[s * 4 + 0], q1 = part[s * 4 + 1], q2 = part[s * 4 + 2], q3 = part[s * 4 + 3];
+    const float4 q0 = part[s], q1 = part[npoints + s], q2 = part[2 * npoints + s], q3 = part[3 * npoints + s];
     const double f = ((double)q0.x + (double)q1.x) + ((double)q2.x + (double)q3.x);
     gradf[s] = make_float4((q0.y + q1.y) + (q2.y + q3.y), (q0.z + q1.z) + (q2.z + q3.z),
                            (q0.w + q1.w) + (q2.w + q3.w), (float)f);
@@ -1617,7 +1622,7 @@ __device__ __forceinline__ void b_bwd_point_finalize(const float4* __restrict__ 
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
 #pragma unroll
     for (int slot = 0; slot < 4; ++slot) {
-      const float4 q = part[(s * 3 + c) * 4 + slot];
+      const float4 q = part[(c * 4 + slot) * npoints + s];
       dn[c] += q.x;
       g0 += q.y;
       g1 += q.z;
@@ -1736,7 +1741,7 @@ template <int RES, int MODE, int MAXJ>
 __global__ __launch_bounds__(rows_block(RES)) void k_c2r_gather(const Batch<MAXJ> B) {
   PSR_JOB(RES);
   float* out = MODE == MODE_DBG ? J.aux_out : J.chi;
-  b_c2r_gather<RES, MODE>(w.Y, out, sv.hdr, sv.sorted, sv.off, w.part, B.tw, bid);
+  b_c2r_gather<RES, MODE>(w.Y, out, sv.hdr, sv.sorted, sv.off, w.part, J.P, B.tw, bid);
 }
 
 template <int RES, int MODE, int MAXJ>
@@ -1752,7 +1757,7 @@ __global__ __launch_bounds__(Plane<RES>::BLOCK) __attribute__((amdgpu_waves_per_
 void k_plane_inv(const Batch<MAXJ> B) {
   PSR_JOB(RES);
   float* outp = MODE == PI_DBG ? J.aux_out : J.chi;
-  b_plane_inv<RES, MODE>(w.X, outp, sv.hdr, sv.sorted, sv.off, w.part, B.tw, bid);
+  b_plane_inv<RES, MODE>(w.X, outp, sv.hdr, sv.sorted, sv.off, w.part, J.P, B.tw, bid);
 }
 
 template <int RES, int MAXJ>

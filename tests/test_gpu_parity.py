@@ -115,6 +115,11 @@ def test_forward_matches_oracle(psr, dev, res, P, kind, sigma):
     chi, saved = psr.forward(to_dev(sh.points, dev), to_dev(sh.normals, dev), res, sigma)
     assert psr.status(saved) == 0
     ref, aux = oracle.forward(sh.points, sh.normals, res, sigma)
+    if kind == "uniform":
+        # random normals: |c| can be small against max|chi'|, so chi is held
+        # through the conditioning-aware comparison (chi' and c at the plain bar)
+        assert_forward_close(psr, chi, saved, ref, aux)
+        return
     assert max_rel(host(chi), ref) < E_CHI
     sc = psr.scalars(saved)
     scale_ref = abs(aux["cscale"])
