@@ -11,6 +11,10 @@
 #ifndef PSR_J0_THREADS
 #define PSR_J0_THREADS 256
 #endif
+// The j0 passes below 256: smaller workgroups, more of them per CU.
+#ifndef PSR_J0_THREADS_SMALL
+#define PSR_J0_THREADS_SMALL 128
+#endif
 // Smallest grid size whose plane passes split each plane into two parts.
 #ifndef PSR_PLANE_SPLIT_MIN
 #define PSR_PLANE_SPLIT_MIN 256
@@ -30,7 +34,9 @@ __host__ __device__ constexpr int tile_cols(int res) { return imin(res, PSR_COL_
 __host__ __device__ constexpr int cols_block(int res) { return tile_cols(res) * plan_TPL(res); }
 
 // The fused j0 passes (three transforms per line) may use their own tile.
-__host__ __device__ constexpr int tile_j0(int res) { return imin(res, PSR_J0_THREADS / plan_TPL(res)); }
+__host__ __device__ constexpr int tile_j0(int res) {
+  return imin(res, (res < 256 ? PSR_J0_THREADS_SMALL : PSR_J0_THREADS) / plan_TPL(res));
+}
 __host__ __device__ constexpr int j0_block(int res) { return tile_j0(res) * plan_TPL(res); }
 
 // Row passes (splat + r2c and c2r + gather along j2; half-length complex
