@@ -76,8 +76,8 @@ def stage_bytes(r: int, P: int, fp: float = 1.0, ft: float = 1.0) -> dict:
     N4 = 4 * r ** 3
     return {
         "bin": 24 * P + 32 * P * 2 + 8 * P,
-        "P1_splat_r2c": 32 * P + 3 * S * fp,           # sorted points in, 3 half-spectra of live planes out
-        "P2_fft_j1": 3 * S * fp + 2 * S * fp,          # live lines of 3 channels in, v~_0 and merged W of live planes out
+        "P1_splat_r2c": 32 * P + 3 * S * ft,           # sorted points in, 3 half-spectra of touched row tiles out
+        "P2_fft_j1": 3 * S * ft + 2 * S * fp,          # touched tile segments of 3 channels in, v~_0 and merged W of live planes out
         "P3_fft_j0_spectral_ifft_j0": 2 * S * fp + S,  # live planes of the 2 in, chi~ (after the k0 inverse) out
         "P4_ifft_j1": 2 * S,
         "P5_c2r_gather": S + N4 + 32 * P + 64 * P,     # chi' written, gather partials

@@ -34,6 +34,9 @@ struct SavedHeader {
   double scale;     // m / |c|
   double chi0;      // chi'(0,0,0)
   uint32_t live[16];  // bit j0: some point's corners reach plane j0 (j0 < 512)
+  // bit j0 * row_tiles(res) + tb: some point's corners reach row tile tb of
+  // plane j0 (res * row_tiles(res) <= 8192)
+  uint32_t tlive[256];
 };
 
 // Backward scalars computed on the device from the FP64 reductions.

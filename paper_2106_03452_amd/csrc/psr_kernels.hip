@@ -375,6 +375,24 @@ __device__ __forceinline__ void b_live_planes(const int* __restrict__ off, Saved
   }
   __syncthreads();
   if (t < 16) hdr->live[t] = bits[t];
+  // the same per row tile
+  constexpr int NT = row_tiles(RES), NTB = RES * NT, NW = (NTB + 31) / 32;
+  static_assert(NTB <= 32 * 256 && 32 % NT == 0, "tile bitmap: one word holds the tiles of whole planes");
+  __shared__ uint32_t tbits[NW];
+  for (int e = t; e < NW; e += blockDim.x) tbits[e] = 0;
+  __syncthreads();
+  for (int e = t; e < NTB; e += blockDim.x)
+    if (tile_ranges<RES>(off, e / NT, e % NT).total > 0) atomicOr(&tbits[e >> 5], 1u << (e & 31));
+  __syncthreads();
+  for (int e = t; e < NW; e += blockDim.x) hdr->tlive[e] = tbits[e];
+}
+
+// The row-tile bits of plane j0 (bit tb), from the tile bitmap.
+template <int RES>
+__device__ __forceinline__ uint32_t plane_tiles(const uint32_t* __restrict__ tlive, int j0) {
+  constexpr int NT = row_tiles(RES);
+  const int e = j0 * NT;
+  return (tlive[e >> 5] >> (e & 31)) & (NT == 32 ? ~0u : ((1u << NT) - 1u));
 }
 
 __device__ __forceinline__ bool live_bit(const uint32_t* live, int j0) { return (live[j0 >> 5] >> (j0 & 31)) & 1u; }
@@ -632,16 +650,9 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
   if constexpr (MODE != MODE_LOADV) R = tile_ranges<RES>(off, j0, tb);
   const int total = R.total;
   if constexpr (MODE == MODE_SPLAT) {
-    // no point reaches the plane: P2 takes its lines as zero without reading them
-    if (!plane_live<RES>(off, j0)) return;
-    // no point touches this tile: its rows and their spectra are zero
-    if (total == 0) {
-      for (int e = t; e < H * (TR / 2); e += BR) {
-        const int l = 2 * (e % (TR / 2)), k = e / (TR / 2);
-        *reinterpret_cast<float4*>(out + (((int64_t)c * H + k) * RES + j0) * RES + a0 + l) = make_float4(0, 0, 0, 0);
-      }
-      return;
-    }
+    // no point touches this row tile (of a plane some point may reach): its
+    // rows and their spectra are zero; P2 takes them as zero without reading
+    if (total == 0) return;
   }
 
   float3 sqa = make_float3(1.0f, 0.0f, 1.0f);
@@ -757,26 +768,30 @@ __device__ __forceinline__ void b_axis1_fwd(const cf* __restrict__ in, cf* __res
   const int a0 = tb * TC;
   const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
   const cf* src = in + ((int64_t)k2 * RES + a0 + l) * RES;
-  // SKIP: lines of a plane no point reaches were never written; they are zero,
-  // and P3 does not read their transforms either
+  // SKIP: the row-tile segments of a line (element j1 in tile j1 / TR) that no
+  // point touches were never written by P1; they are zero. Lines of a plane
+  // no point reaches are all zero, and P3 does not read their transforms.
+  constexpr int TR = tile_rows(RES);
   __shared__ int line_live[SKIP ? TC : 1];
-  const bool live = !SKIP || live_bit(livebits, a0 + l);
+  const uint32_t tiles = SKIP ? plane_tiles<RES>(livebits, a0 + l) : ~0u;
+  const bool live = tiles != 0;
+  auto seg = [&](int v) { return !SKIP || ((tiles >> ((lt + TPL * v) / TR)) & 1u); };
   if (SKIP && lt == 0) line_live[l] = live;
   cf reg[E];
   if (!MERGE || c == 0) {
 #pragma unroll
-    for (int v = 0; v < E; ++v) reg[v] = live ? src[c * CH + lt + TPL * v] : cf{0.0f, 0.0f};
+    for (int v = 0; v < E; ++v) reg[v] = seg(v) ? src[c * CH + lt + TPL * v] : cf{0.0f, 0.0f};
     fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
   } else {
     cf acc[E];
 #pragma unroll
-    for (int v = 0; v < E; ++v) reg[v] = live ? src[2 * CH + lt + TPL * v] : cf{0.0f, 0.0f};
+    for (int v = 0; v < E; ++v) reg[v] = seg(v) ? src[2 * CH + lt + TPL * v] : cf{0.0f, 0.0f};
     fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
     const float k2f = kappa_odd(k2, RES);
 #pragma unroll
     for (int v = 0; v < E; ++v) {
       acc[v] = cf{k2f * reg[v].x, k2f * reg[v].y};
-      reg[v] = live ? src[CH + lt + TPL * v] : cf{0.0f, 0.0f};
+      reg[v] = seg(v) ? src[CH + lt + TPL * v] : cf{0.0f, 0.0f};
     }
     fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
 #pragma unroll
@@ -1715,7 +1730,7 @@ __global__ __launch_bounds__(rows_block(RES)) void k_splat_r2c(const Batch<MAXJ>
 template <int RES, bool MERGE, bool SKIP, int MAXJ>
 __global__ __launch_bounds__(cols_block(RES)) void k_axis1_fwd(const Batch<MAXJ> B) {
   PSR_JOB(RES);
-  b_axis1_fwd<RES, MERGE, SKIP>(w.X, w.Y, B.tw, sv.hdr->live, bid);
+  b_axis1_fwd<RES, MERGE, SKIP>(w.X, w.Y, B.tw, sv.hdr->tlive, bid);
 }
 
 template <int RES, bool SKIP, int MAXJ>

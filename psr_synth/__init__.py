@@ -23,8 +23,8 @@ import numpy as np
 
 __all__ = [
     "rng_for", "sphere", "torus", "superellipsoid", "random_rotation",
-    "Shape", "config_c1", "config_c2", "config_c3", "config_c4", "config_c5",
-    "random_shape", "tiny_case",
+    "Shape", "config_c1", "config_c2", "config_c2_outliers", "config_c3", "config_c4", "config_c5",
+    "random_shape", "tiny_case", "loss_gradient",
 ]
 
 
@@ -186,6 +186,23 @@ def config_c2(seed: int = 1, P: int = 20000) -> Shape:
     return Shape(128, 2.0, _f32(pj), _f32(n), _f32(p), _f32(n), kind="torus+sphere")
 
 
+def config_c2_outliers(seed: int = 1, P: int = 20000, frac: float = 0.5) -> Shape:
+    """C2 with a fraction of its points replaced by outliers: uniform in [0,1)^3,
+    random directions, |n| ~ U[0, 0.05] (the paper's outlier setting; the
+    low-locality worst case for binning). ``points_clean``/``normals_clean``
+    are C2's clean surface points at the same indices."""
+    base = config_c2(seed, P)
+    rng = rng_for(seed + 1000)
+    k = int(round(frac * P))
+    idx = rng.choice(P, k, replace=False)
+    p = base.points.astype(np.float64)
+    n = base.normals.astype(np.float64)
+    p[idx] = rng.uniform(0.0, 1.0, (k, 3))
+    n[idx] = _unit(rng.standard_normal((k, 3))) * rng.uniform(0.0, 0.05, (k, 1))
+    return Shape(128, 2.0, _f32(p), _f32(n), base.points_clean, base.normals_clean, kind="torus+sphere+outliers",
+                 meta=dict(outliers=k))
+
+
 def config_c3(seed: int = 2, P: int = 100000, table=(2048, 4096)) -> Shape:
     """256^3, sigma 2; one random superellipsoid, noisy (renormalised) normals."""
     rng = rng_for(seed)
@@ -241,6 +258,12 @@ def config_c5(seed: int = 4, n_requests: int = 2000):
         reqs.append((random_shape(rng, res, P), bwd))
     arrivals_unit = rng.exponential(1.0, n_requests)
     return reqs, arrivals_unit
+
+
+def loss_gradient(res: int, seed: int) -> np.ndarray:
+    """A dense stand-in for dL/dchi: float32 standard normal on the res^3 grid
+    (PCG64(seed), float32 draws), the same array wherever it is drawn."""
+    return rng_for(seed).standard_normal((res, res, res), dtype=np.float32)
 
 
 def tiny_case(seed: int, res: int, P: int, sigma: float = 2.0, kind: str = "sphere") -> Shape:

@@ -6,6 +6,7 @@ C2: 128^3, 20,000 points (torus U sphere, jittered), loss mean((chi - chi_t)^2)
     differences of the oracle (tests/golden/c2_fd.json).
 C3: 256^3, 100,000 points on a superellipsoid with noisy normals, the same
     loss with chi_t from the clean normals; everything against the oracle.
+    The same cloud on 512^3 (the largest grid) against stored oracle samples.
 Each side computes its own target chi_t and loss gradient G.
 """
 import json
@@ -99,6 +100,52 @@ def test_c3_forward_backward_vs_oracle(dev):
     e_chi, e_dc, e_dn = max_rel(chi_g, chi_r), l2_rel(dp_g, dc_r), l2_rel(dn_g, dn_r)
     print(f"C3 e_chi={e_chi:.3e} e_dpoints={e_dc:.3e} e_dnormals={e_dn:.3e}")
     assert e_chi < 1e-5 and e_dc < 1e-4 and e_dn < 1e-4
+
+
+def test_c2_with_half_outliers(dev):
+    """C2 with 50 % of the points replaced by uniform outliers with short random
+    normals: the worst locality for the binning and the splat; chi and both
+    gradients against the oracle (dense random loss gradient)."""
+    from paper_2106_03452_amd import function as F
+    announce("C2 with 50% outliers 128^3 fwd+bwd")
+    sh = S.config_c2_outliers()
+    G = S.loss_gradient(128, 128)
+    chi, saved = F.forward(to_dev(sh.points, dev), to_dev(sh.normals, dev), 128, sh.sigma)
+    assert F.status(saved) == 0
+    dp, dn = F.backward(chi, saved, to_dev(G, dev), sh.P, 128, sh.sigma)
+    ref, aux = oracle.forward(sh.points, sh.normals, 128, sh.sigma)
+    dc_r, dn_r = oracle.backward(aux, G)
+    e_chi, e_dc, e_dn = max_rel(host(chi), ref), l2_rel(host(dp), dc_r), l2_rel(host(dn), dn_r)
+    print(f"C2 + outliers e_chi={e_chi:.3e} e_dpoints={e_dc:.3e} e_dnormals={e_dn:.3e}")
+    assert e_chi < 1e-5 and e_dc < 1e-4 and e_dn < 1e-4
+
+
+def test_c3_cloud_at_512_vs_stored_oracle(dev):
+    """The largest grid: the C3 cloud (100k points) on 512^3 against FP64 oracle
+    samples written by tests/golden/make_c3_512.py (chi at 8192 voxels over
+    max|chi| of the whole grid, mu and c, both gradients at 4096 points; the
+    loss gradient is psr_synth.loss_gradient(512, 512) on both sides)."""
+    from paper_2106_03452_amd import function as F
+    g = np.load(os.path.join(GOLDEN, "c3_512_samples.npz"))
+    sh = S.config_c3()
+    announce("C3 cloud at 512^3 vs stored oracle samples")
+    chi, saved = F.forward(to_dev(sh.points, dev), to_dev(sh.normals, dev), 512, sh.sigma)
+    assert F.status(saved) == 0
+    G = to_dev(S.loss_gradient(512, 512), dev)
+    dp, dn = F.backward(chi, saved, G, sh.P, 512, sh.sigma)
+    torch.cuda.synchronize()
+    del G
+    sc = F.scalars(saved)
+    c = abs(float(g["cscale"]))
+    chi_s = host(chi.reshape(-1)[torch.as_tensor(g["vox"], device=dev)])
+    e_chi = float(np.abs(chi_s.astype(np.float64) - g["chi"]).max() / float(g["chi_max"]))
+    pts = torch.as_tensor(g["pts"], device=dev)
+    e_dc, e_dn = l2_rel(host(dp[pts]), g["dpoints"]), l2_rel(host(dn[pts]), g["dnormals"])
+    print(f"C3 cloud at 512^3: e_chi={e_chi:.3e} (8192 voxels) e_dpoints={e_dc:.3e} e_dnormals={e_dn:.3e} (4096 points)")
+    assert e_chi < 1e-5
+    assert abs(sc["mean"] - float(g["mu"])) <= 1e-5 * c
+    assert abs(sc["cscale"] - float(g["cscale"])) <= 1e-5 * c
+    assert e_dc < 1e-4 and e_dn < 1e-4
 
 
 def test_c1_sphere_is_an_indicator(dev):
