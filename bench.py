@@ -84,7 +84,8 @@ def stage_bytes(r: int, P: int, fp: float = 1.0, ft: float = 1.0) -> dict:
         "fwd_reduce": 64 * P + 16 * P,
         "normalize": 2 * N4,
         "bwd_reduce": 2 * N4,
-        "B1_cotangent_r2c": N4 + 32 * P + S,
+        "B1a_reduce_r2c": 2 * N4 + S * (1 - ft),      # G and chi in (FP64 partials), H = sG spectra of point-free tiles out
+        "B1_cotangent_r2c": N4 * ft + 32 * P + S * ft, # the tiles with points: G in, splat of W, spectra out
         "B2_fft_j1": 2 * S,
         "B3_fft_j0_conjop_ifft_j0": S + 2 * S * fp,    # 1 in; kappa_0 channel and U out on live planes
         "B4_ifft_j1": 2 * S * fp + 3 * S * ft,         # live planes in, touched tiles out
@@ -114,6 +115,7 @@ KERNEL_STAGES = [
     (r"k_c2r_gather<{r}, 0,", "P5_c2r_gather"),
     (r"k_normalize<{r},", "normalize"),
     (r"k_splat_r2c<{r}, 1,", "B1_cotangent_r2c"),
+    (r"k_splat_r2c<{r}, 4,", "B1a_reduce_r2c"),
     (r"k_axis1_fwd<{r}, false,", "B2_fft_j1"),
     (r"k_bwd_axis0<{r},", "B3_fft_j0_conjop_ifft_j0"),
     (r"k_axis1_inv<{r}, true,", "B4_ifft_j1"),

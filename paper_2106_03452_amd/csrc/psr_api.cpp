@@ -140,7 +140,7 @@ const char* const kStageNames[psr::NUM_STAGES] = {
     "bin", "P1_splat_r2c", "P2_fft_j1", "P3_fft_j0_spectral_ifft_j0", "P4_ifft_j1", "P5_c2r_gather",
     "fwd_reduce", "normalize", "bwd_reduce", "B1_cotangent_r2c", "B2_fft_j1", "B3_fft_j0_conjop_ifft_j0",
     "B4_ifft_j1", "B5_c2r_gather", "bwd_finalize", "P12_splat_r2c_fft_j1", "P45_ifft_j1_c2r_gather",
-    "B12_cotangent_r2c_fft_j1", "B45_ifft_j1_c2r_gather"};
+    "B12_cotangent_r2c_fft_j1", "B45_ifft_j1_c2r_gather", "B1a_reduce_r2c"};
 
 }  // namespace
 

@@ -65,6 +65,7 @@ enum Stage {
   STAGE_P45,  // plane pass: P4 + P5
   STAGE_B12,  // plane pass: B1 + B2
   STAGE_B45,  // plane pass: B4 + B5
+  STAGE_B1A,  // two-pass path: backward reductions + r2c of point-free row tiles
   NUM_STAGES
 };
 
@@ -84,7 +85,12 @@ __host__ __device__ inline WsLayout ws_layout(int res, int64_t P) {
   L.bs = o;
   o += align256(sizeof(BwdScalars));
   L.blockpart = o;
-  o += align256(kRedBlocks * 16);
+  {
+    // FP64 block partials: the grid-stride reductions (kRedBlocks) or one
+    // per row tile of the backward's first row pass
+    const size_t tiles = (size_t)res * (size_t)row_tiles(res);
+    o += align256((tiles > (size_t)kRedBlocks ? tiles : (size_t)kRedBlocks) * 16);
+  }
   L.X = o;
   o += align256(spec);
   L.Y = o;

@@ -429,8 +429,11 @@ __device__ __forceinline__ void b_scatter(const PointRec* __restrict__ tmp, cons
 // MODE_BWDH : H = s G + alpha W - Q delta_0 (1 channel)   [backward]
 // MODE_LOADV: v_c loaded from global                     [spectral test hook]
 // MODE_VOUT : splat only, rows written to global v_c      [splat test hook]
+// MODE_BWDA : the FP64 partials of S_G and S_Gchi per row tile, and H = s G
+//             for the row tiles that W and delta_0 do not reach  [backward,
+//             before MODE_BWDH, which then takes only the other tiles]
 // ---------------------------------------------------------------------------
-enum { MODE_SPLAT = 0, MODE_BWDH = 1, MODE_LOADV = 2, MODE_VOUT = 3 };
+enum { MODE_SPLAT = 0, MODE_BWDH = 1, MODE_LOADV = 2, MODE_VOUT = 3, MODE_BWDA = 4 };
 
 // blocks of the grid-stride FP64 reduction over RES^3 / 4 float4 (at least 1)
 template <int RES>
@@ -619,6 +622,71 @@ __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__
 }
 
 
+// Rows [a0, a0 + NROWS) of plane j0: the FP64 sums of G and G chi over them
+// into *part (fixed order: per thread, then wavefront shuffles, then
+// wavefronts in order), and, when fill, rows H = s G in LDS as fill_rows
+// lays them out. Ends with a barrier.
+template <int RES, int NROWS, int BLOCK>
+__device__ __forceinline__ void bwda_rows(cf* rows, const float* __restrict__ G, const float* __restrict__ chi,
+                                          float s, int j0, int a0, double2* __restrict__ part, bool fill) {
+  constexpr int M = RES / 2, NV = NROWS * M / 2, IT = (NV + BLOCK - 1) / BLOCK;
+  constexpr int NW = (BLOCK + 63) / 64, W = BLOCK < 64 ? BLOCK : 64;
+  const int t = threadIdx.x;
+  const int64_t base = ((int64_t)j0 * RES + a0) * RES;
+  const float4* g4 = reinterpret_cast<const float4*>(G + base);
+  const float4* c4 = reinterpret_cast<const float4*>(chi + base);
+  float4 gb[IT], cb[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = t + it * BLOCK;
+    if (e < NV) {
+      gb[it] = g4[e];
+      cb[it] = c4[e];
+    }
+  }
+  double a = 0.0, b = 0.0;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = t + it * BLOCK;
+    if (e < NV) {
+      const float4 g = gb[it], c = cb[it];
+      a += ((double)g.x + (double)g.y) + ((double)g.z + (double)g.w);
+      b += ((double)g.x * c.x + (double)g.y * c.y) + ((double)g.z * c.z + (double)g.w * c.w);
+    }
+  }
+#pragma unroll
+  for (int d = W / 2; d > 0; d >>= 1) {
+    a += __shfl_xor(a, d, W);
+    b += __shfl_xor(b, d, W);
+  }
+  __shared__ double wsum[2][NW];
+  if ((t & 63) == 0) {
+    wsum[0][t >> 6] = a;
+    wsum[1][t >> 6] = b;
+  }
+  if (fill) {
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * BLOCK;
+      if (e < NV) {
+        const int mm = (2 * e) % M, l = (2 * e) / M;
+        rows[rpos<M>(l, mm)] = cf{gb[it].x * s, gb[it].y * s};
+        rows[rpos<M>(l, mm + 1)] = cf{gb[it].z * s, gb[it].w * s};
+      }
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      sa += wsum[0][w];
+      sb += wsum[1][w];
+    }
+    *part = make_double2(sa, sb);
+  }
+}
+
 template <int RES, int MODE>
 __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
                                                               const int* __restrict__ off,
@@ -627,7 +695,8 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
                                                               const double2* __restrict__ bpart,
                                                               const SavedHeader* __restrict__ hdr,
                                                               const cf* __restrict__ tw, cf* __restrict__ out,
-                                                              float* __restrict__ vout, int bid) {
+                                                              float* __restrict__ vout, const float* __restrict__ chi_in,
+                                                              double2* __restrict__ bpart_w, int bid) {
   constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_block(RES);
   constexpr int TPL = plan_TPL(M), E = plan_E(M), LS = row_ls(M);
   constexpr int64_t N3 = (int64_t)RES * RES * RES;
@@ -655,9 +724,21 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
     if (total == 0) return;
   }
 
-  float3 sqa = make_float3(1.0f, 0.0f, 1.0f);
-  if constexpr (MODE == MODE_BWDH) sqa = bwd_scalars<BR>(bpart, bwd_reduce_blocks<RES>(), hdr, bs, bid == 0);
-  fill_rows<RES, TR, BR, MODE == MODE_VOUT ? MODE_SPLAT : MODE>(rows, sorted, R, gin, sqa, j0, a0, c);
+  // the row tile holding vertex 0 (workgroup 0) carries the -Q delta_0 term
+  const bool has_delta = j0 == 0 && a0 == 0;
+  if constexpr (MODE == MODE_BWDA) {
+    // rows of tiles that W and delta_0 reach wait for the reductions (MODE_BWDH)
+    const bool later = total > 0 || has_delta;
+    bwda_rows<RES, TR, BR>(rows, gin, chi_in, (float)hdr->scale, j0, a0, bpart_w + bid, !later);
+    if (later) return;
+  } else {
+    float3 sqa = make_float3(1.0f, 0.0f, 1.0f);
+    if constexpr (MODE == MODE_BWDH) {
+      if (total == 0 && !has_delta) return;  // done by MODE_BWDA
+      sqa = bwd_scalars<BR>(bpart, RES * NT, hdr, bs, bid == 0);
+    }
+    fill_rows<RES, TR, BR, MODE == MODE_VOUT ? MODE_SPLAT : MODE>(rows, sorted, R, gin, sqa, j0, a0, c);
+  }
 
   if constexpr (MODE == MODE_VOUT) {
     for (int e = t; e < TR * RES; e += BR) {
@@ -1722,9 +1803,9 @@ __global__ __launch_bounds__(256) void k_scatter(const Batch<MAXJ> B) {
 template <int RES, int MODE, int MAXJ>
 __global__ __launch_bounds__(rows_block(RES)) void k_splat_r2c(const Batch<MAXJ> B) {
   PSR_JOB(RES);
-  const float* gin = MODE == MODE_BWDH ? J.dchi : J.aux_in;
+  const float* gin = MODE == MODE_BWDH || MODE == MODE_BWDA ? J.dchi : J.aux_in;
   b_splat_r2c<RES, MODE>(sv.sorted, sv.off, gin, w.bs, (const double2*)w.blockpart, sv.hdr, B.tw, w.X, J.aux_out,
-                         bid);
+                         J.chi, (double2*)w.blockpart, bid);
 }
 
 template <int RES, bool MERGE, bool SKIP, int MAXJ>
@@ -1897,14 +1978,19 @@ static int seq_backward(Exec& x, const JobArg* J, int n) {
   using G = Grid<RES>;
   int rc = 0;
   auto c = [](int v) { return [v](const JobArg&) { return v; }; };
-  x.begin(STAGE_BWD_REDUCE);
-  rc |= launch<MAXJ>(x, k_bwd_reduce<RES, MAXJ>, 256, J, n, c(bwd_reduce_blocks<RES>()));
-  x.end(STAGE_BWD_REDUCE);
   if constexpr (use_plane(RES)) {
+    x.begin(STAGE_BWD_REDUCE);
+    rc |= launch<MAXJ>(x, k_bwd_reduce<RES, MAXJ>, 256, J, n, c(bwd_reduce_blocks<RES>()));
+    x.end(STAGE_BWD_REDUCE);
     x.begin(STAGE_B12);
     rc |= launch<MAXJ>(x, k_plane_fwd<RES, PF_BWDH, MAXJ>, Plane<RES>::BLOCK, J, n, c(RES * Plane<RES>::KP));
     x.end(STAGE_B12);
   } else {
+    // the reductions ride on the first row pass, which also transforms the
+    // row tiles that need no backward scalar; the second takes the rest
+    x.begin(STAGE_B1A);
+    rc |= launch<MAXJ>(x, k_splat_r2c<RES, MODE_BWDA, MAXJ>, G::BR, J, n, c(G::rows));
+    x.end(STAGE_B1A);
     x.begin(STAGE_B1);
     rc |= launch<MAXJ>(x, k_splat_r2c<RES, MODE_BWDH, MAXJ>, G::BR, J, n, c(G::rows));
     x.end(STAGE_B1);
