@@ -16,9 +16,12 @@
 // two axes per kernel with a whole j0 plane on chip; at 256^3 only P45 does.
 // The backward runs the adjoint of every step (FP64 sums of G and G*chi, the
 // cotangent H, conjugate operator, 3 inverse channels, gather of dL/dv), with
-// the same pass structure (B1..B5, B12, B45). Planes and row tiles that no
-// point reaches are skipped where their values are zero or unused. The splat
-// accumulates fixed-point integers in LDS (bitwise reproducible).
+// the same pass structure (B1..B5, B12, B45); on the two-pass path the sums
+// ride on a first cotangent pass (B1a) that also transforms the row tiles
+// needing no backward scalar. Planes and row tiles that no point reaches are
+// skipped where their values are zero or unused (bitmaps from the bin
+// offsets). The splat accumulates fixed-point integers in LDS (bitwise
+// reproducible) unless a span is very dense.
 //
 // Layouts (complex64 unless noted; H = r/2 + 1 half-spectrum planes):
 //   A[c][k2][j0][j1]   P1 out, P2 in   (3 channels fwd, 1 bwd)
