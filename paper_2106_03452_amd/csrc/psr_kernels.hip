@@ -1,7 +1,8 @@
 // gfx950 kernels of the differentiable Poisson solver (Peng et al., NeurIPS 2021).
 //
 // Pipeline of one forward solve (main Sec. 3.1, Eqs. 2-4; supplement Sec. A):
-//   bin      points -> row-tile buckets (count, scan, scatter)
+//   bin      points -> row-tile buckets (count, scan, scatter; below 512^3
+//            every scatter workgroup scans the bin counts in LDS)
 //   P1       splat normals into LDS rows + real-to-complex FFT along j2
 //            (supplement A.1 rasterisation fused with the first FFT axis)
 //   P2       FFT along j1 (3 channels in; out v~_0 and the merged channel
@@ -424,6 +425,45 @@ __device__ __forceinline__ void b_scatter(const PointRec* __restrict__ tmp, cons
   if (i >= npoints) return;
   const int2 cr = colrank[i];
   sorted[off[cr.x] + cr.y] = tmp[i];
+}
+
+// Grids with at most kLdsBins bins skip the one-workgroup scan kernel: every
+// scatter workgroup forms the same exclusive prefix sum of the counts in LDS
+// (BLOCK threads, consecutive runs of bins per thread), and workgroup 0 also
+// publishes the offsets and the liveness bitmaps.
+constexpr int kLdsBins = 4096;
+
+template <int NB, int BLOCK>
+__device__ __forceinline__ void scan_to_lds(const int* __restrict__ counts, int* soff) {
+  constexpr int PT = (NB + BLOCK - 1) / BLOCK, NW = BLOCK / 64;
+  static_assert(BLOCK % 64 == 0, "whole wavefronts");
+  __shared__ int wtot[NW];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  int v[PT], sum = 0;
+#pragma unroll
+  for (int k = 0; k < PT; ++k) {
+    const int i = t * PT + k;
+    v[k] = i < NB ? counts[i] : 0;
+    sum += v[k];
+  }
+  int x = sum;  // inclusive scan of the thread sums within the wavefront
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wtot[wid] = x;
+  __syncthreads();
+  int run = x - sum;
+  for (int q = 0; q < wid; ++q) run += wtot[q];
+#pragma unroll
+  for (int k = 0; k < PT; ++k) {
+    const int i = t * PT + k;
+    if (i < NB) soff[i] = run;
+    run += v[k];
+  }
+  if (t == BLOCK - 1) soff[NB] = run;  // the last thread's run ends at NB: the total
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -1803,6 +1843,20 @@ __global__ __launch_bounds__(256) void k_scatter(const Batch<MAXJ> B) {
   b_scatter(w.tmp, w.colrank, sv.off, sv.sorted, J.P, bid);
 }
 
+template <int RES, int MAXJ>
+__global__ __launch_bounds__(256) void k_scan_scatter(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  constexpr int NB = num_bins(RES);
+  static_assert(NB <= kLdsBins, "bins fit in LDS");
+  __shared__ int soff[NB + 1];
+  scan_to_lds<NB, 256>(w.counts, soff);
+  if (bid == 0) {
+    for (int e = threadIdx.x; e <= NB; e += 256) sv.off[e] = soff[e];
+    b_live_planes<RES>(soff, sv.hdr);
+  }
+  b_scatter(w.tmp, w.colrank, soff, sv.sorted, J.P, bid);
+}
+
 template <int RES, int MODE, int MAXJ>
 __global__ __launch_bounds__(rows_block(RES)) void k_splat_r2c(const Batch<MAXJ> B) {
   PSR_JOB(RES);
@@ -1936,8 +1990,12 @@ static int seq_forward(Exec& x, const JobArg* J, int n) {
   x.begin(STAGE_BIN);
   rc |= launch<MAXJ>(x, k_init<RES, MAXJ>, 256, J, n, c(G::init_blocks));
   rc |= launch<MAXJ>(x, k_bin<RES, MAXJ>, 256, J, n, [](const JobArg& a) { return nblk(a.P, kBinChunk); });
-  rc |= launch<MAXJ>(x, k_scan<RES, MAXJ>, 1024, J, n, c(1));
-  rc |= launch<MAXJ>(x, k_scatter<RES, MAXJ>, 256, J, n, [](const JobArg& a) { return nblk(a.P, 256); });
+  if constexpr (num_bins(RES) <= kLdsBins) {
+    rc |= launch<MAXJ>(x, k_scan_scatter<RES, MAXJ>, 256, J, n, [](const JobArg& a) { return nblk(a.P, 256); });
+  } else {
+    rc |= launch<MAXJ>(x, k_scan<RES, MAXJ>, 1024, J, n, c(1));
+    rc |= launch<MAXJ>(x, k_scatter<RES, MAXJ>, 256, J, n, [](const JobArg& a) { return nblk(a.P, 256); });
+  }
   x.end(STAGE_BIN);
   if constexpr (use_plane(RES)) {
     x.begin(STAGE_P12);
@@ -2062,8 +2120,12 @@ static int debug_splat_res(Exec& x, const JobArg& job) {
   int rc = 0;
   rc |= launch<1>(x, k_init<RES, 1>, 256, &job, 1, c(G::init_blocks));
   rc |= launch<1>(x, k_bin<RES, 1>, 256, &job, 1, [](const JobArg& a) { return nblk(a.P, kBinChunk); });
-  rc |= launch<1>(x, k_scan<RES, 1>, 1024, &job, 1, c(1));
-  rc |= launch<1>(x, k_scatter<RES, 1>, 256, &job, 1, [](const JobArg& a) { return nblk(a.P, 256); });
+  if constexpr (num_bins(RES) <= kLdsBins) {
+    rc |= launch<1>(x, k_scan_scatter<RES, 1>, 256, &job, 1, [](const JobArg& a) { return nblk(a.P, 256); });
+  } else {
+    rc |= launch<1>(x, k_scan<RES, 1>, 1024, &job, 1, c(1));
+    rc |= launch<1>(x, k_scatter<RES, 1>, 256, &job, 1, [](const JobArg& a) { return nblk(a.P, 256); });
+  }
   rc |= launch<1>(x, k_splat_r2c<RES, MODE_VOUT, 1>, G::BR, &job, 1, c(3 * G::rows));
   return rc ? -4 : 0;
 }
