@@ -422,8 +422,8 @@ def main():
         print(json.dumps(ingest_counters(*args.ingest_counters), indent=1))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the solver runs on a single MI355X (its multi-GPU slab "
-              "decomposition is a design, not part of this build). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the solver runs on a single MI355X (a multi-GPU slab "
+              "decomposition is described, not implemented). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
