@@ -1224,10 +1224,13 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
   // Hermitian half-spectrum X[0..M] -> packed spectrum Z[0..M) of the
   // even/odd samples: Z = (X_k + X*_{M-k}) + i (X_k - X*_{M-k}) e^{+2 pi i k/r}.
   {
-    constexpr int NP = M / 2 + 1;
+    // k in [0, M/2) first, in runs of M/2 per row (whole 16-element blocks of
+    // the padded LDS line, so the k reads of a 16-lane group hit distinct
+    // banks), then k = M/2, which is its own partner, for every row
+    constexpr int NH = M / 2;
     const cf* twr = rtw;
-    for (int e = t; e < TR * NP; e += BR) {
-      const int k = e % NP, row = e / NP;
+    for (int e = t; e < TR * (NH + 1); e += BR) {
+      const int k = e < TR * NH ? e % NH : NH, row = e < TR * NH ? e / NH : e - TR * NH;
       const int ik = rpos<M>(row, k), im = rpos<M>(row, M - k);
       const cf xk = rows[ik], xm = rows[im];
       {
@@ -1579,9 +1582,11 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
   // Hermitian half-spectrum X[0..M] -> packed spectrum Z[0..M) of the
   // even/odd samples: Z = (X_k + X*_{M-k}) + i (X_k - X*_{M-k}) e^{+2 pi i k/r}.
   {
-    constexpr int NP = M / 2 + 1;
-    for (int e = t; e < RC * NP; e += BLOCK) {
-      const int k = e % NP, row = e / NP;
+    // k in [0, M/2) in runs of M/2 per row, then k = M/2 for every row (as in
+    // the c2r of the row passes)
+    constexpr int NH = M / 2;
+    for (int e = t; e < RC * (NH + 1); e += BLOCK) {
+      const int k = e < RC * NH ? e % NH : NH, row = e < RC * NH ? e / NH : e - RC * NH;
       const int ik = rpos<M>(row, k), im = rpos<M>(row, M - k);
       const cf xk = buf[ik], xm = buf[im];
       {
