@@ -888,7 +888,9 @@ __device__ __forceinline__ void b_axis1_fwd(const cf* __restrict__ in, cf* __res
   const int tb = b % (RES / TC);
   b /= RES / TC;
   const int k2 = b % H;
-  const int c = b / H;  // output channel
+  // output channel; with MERGE the heavier channel-1 workgroups (two
+  // transforms) come first in the grid so that they do not form its tail
+  const int c = MERGE ? 1 - b / H : b / H;
   const int a0 = tb * TC;
   const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
   const cf* src = in + ((int64_t)k2 * RES + a0 + l) * RES;
@@ -1086,7 +1088,9 @@ __device__ __forceinline__ void b_axis1_inv(const cf* __restrict__ in, cf* __res
   const int tb = b % (RES / TC);
   b /= RES / TC;
   const int k2 = b % H;
-  const int c = b / H;  // input channel
+  // input channel; with SPLIT the heavier channel-1 workgroups (two
+  // transforms, two outputs) come first in the grid
+  const int c = SPLIT ? 1 - b / H : b / H;
   const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
   const int j0 = tb * TC + l;
   const cf* src = in + c * CH + ((int64_t)j0 * H + k2) * RES;
