@@ -102,6 +102,17 @@ __device__ __forceinline__ Ranges span_ranges(const int* __restrict__ off, int j
   return R;
 }
 
+// Workgroup -> (row tile T = j0 * row_tiles + tb, channel c < NC) of a row
+// pass over NC channels. The NC workgroups of a tile get ids equal mod 8, so
+// they run on the same XCD and its L2 serves their repeated reads of the
+// tile's point records. The tile count res * row_tiles is a multiple of 8.
+template <int NC>
+__device__ __forceinline__ void tile_of(int bid, int& T, int& c) {
+  const int x = bid & 7, q = bid >> 3;
+  c = q % NC;
+  T = (q / NC) * 8 + x;
+}
+
 template <int RES>
 __device__ __forceinline__ Ranges tile_ranges(const int* __restrict__ off, int j0, int tb) {
   return span_ranges<RES, tile_rows(RES)>(off, j0, tb * tile_rows(RES));
@@ -751,11 +762,10 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
     stage_table<BR>(rtw, tw + RES, M + 1);
   }
   float* rf = reinterpret_cast<float*>(rows);
-  int b = bid;
-  const int tb = b % NT;
-  b /= NT;
-  const int j0 = b % RES;
-  const int c = b / RES;
+  constexpr int NC = MODE == MODE_BWDH || MODE == MODE_BWDA ? 1 : 3;  // channels in the grid
+  int T, c;
+  tile_of<NC>(bid, T, c);
+  const int tb = T % NT, j0 = T / NT;
   const int a0 = tb * TR;
   const int t = threadIdx.x;
   Ranges R{};
@@ -772,13 +782,13 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
   if constexpr (MODE == MODE_BWDA) {
     // rows of tiles that W and delta_0 reach wait for the reductions (MODE_BWDH)
     const bool later = total > 0 || has_delta;
-    bwda_rows<RES, TR, BR>(rows, gin, chi_in, (float)hdr->scale, j0, a0, bpart_w + bid, !later);
+    bwda_rows<RES, TR, BR>(rows, gin, chi_in, (float)hdr->scale, j0, a0, bpart_w + T, !later);
     if (later) return;
   } else {
     float3 sqa = make_float3(1.0f, 0.0f, 1.0f);
     if constexpr (MODE == MODE_BWDH) {
       if (total == 0 && !has_delta) return;  // done by MODE_BWDA
-      sqa = bwd_scalars<BR>(bpart, RES * NT, hdr, bs, bid == 0);
+      sqa = bwd_scalars<BR>(bpart, RES * NT, hdr, bs, T == 0);
     }
     fill_rows<RES, TR, BR, MODE == MODE_VOUT ? MODE_SPLAT : MODE>(rows, sorted, R, gin, sqa, j0, a0, c);
   }
@@ -1174,11 +1184,10 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
   stage_table<BR>(stw, tw + M, M);
   stage_table<BR>(rtw, tw + RES, M + 1);
   const float* rf = reinterpret_cast<const float*>(rows);
-  int b = bid;
-  const int tb = b % NT;
-  b /= NT;
-  const int j0 = b % RES;
-  const int c = b / RES;
+  constexpr int NC = MODE == MODE_BWD ? 3 : 1;  // channels in the grid
+  int T, c;
+  tile_of<NC>(bid, T, c);
+  const int tb = T % NT, j0 = T / NT;
   const int a0 = tb * TR;
   const int t = threadIdx.x;
   Ranges R{};
