@@ -26,7 +26,7 @@
 //
 // Layouts (complex64 unless noted; H = r/2 + 1 half-spectrum planes):
 //   A[c][k2][j0][j1]   P1 out, P2 in   (3 channels fwd, 1 bwd)
-//   B[c][k1][k2][j0]   P2 out, P3 in   (2 fwd, 1 bwd)
+//   B[c][k2][k1][j0]   P2 out, P3 in   (2 fwd, 1 bwd)
 //   C[c][j0][k2][k1]   P3 out, P4/P45 in (1 fwd, 2 bwd); P12 out, P3 in
 //   D[c][k2][j0][j1]   P4 out, P5 in   (1 fwd, 3 bwd)
 // Each pass reads whole contiguous lines or multi-line segments and writes
@@ -879,7 +879,7 @@ __device__ __forceinline__ void store_transposed(cf* rows, const cf* reg, cf* __
 }
 
 // ---------------------------------------------------------------------------
-// P2 / B2: forward FFT along j1. A[c][k2][j0][j1] -> B[c'][k1][k2][j0].
+// P2 / B2: forward FFT along j1. A[c][k2][j0][j1] -> B[c'][k2][k1][j0].
 // MERGE = false (B2): one channel in, one out.
 // MERGE = true (P2): three channels in, two out: v~_0, and
 //   W = kappa_1(k1) v~_1 + kappa_2(k2) v~_2, which is all the j0 pass needs of
@@ -936,14 +936,14 @@ __device__ __forceinline__ void b_axis1_fwd(const cf* __restrict__ in, cf* __res
       reg[v] = cf{acc[v].x + k1f * reg[v].x, acc[v].y + k1f * reg[v].y};
     }
   }
-  store_transposed<RES>(rows, reg, out + ((int64_t)c * RES * H + k2) * RES + a0, (int64_t)H * RES, l, lt, nullptr,
+  store_transposed<RES>(rows, reg, out + ((int64_t)c * H + k2) * RES * RES + a0, (int64_t)RES, l, lt, nullptr,
                         SKIP ? line_live : nullptr);
 }
 
 // ---------------------------------------------------------------------------
 // P3: FFT along j0 of the 3 channels, chi~ = i F(k) sum_d kappa_d^odd v~_d
 // with F = g / (-2 pi |kappa|^2) / N (main Eq. 3; the inverse's 1/N folded
-// in), then inverse FFT along k0. B[2][k1][k2][j0] (or C[2][j0][k2][k1] after
+// in), then inverse FFT along k0. B[2][k2][k1][j0] (or C[2][j0][k2][k1] after
 // a plane pass, IN_C) -> C[1][j0][k2][k1].
 // ---------------------------------------------------------------------------
 // Separable Gaussian of main Eq. 3: g(k) = g1(k0) g1(k1) g1(k2) with
@@ -996,7 +996,7 @@ __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __res
     load_transposed<RES, TC>(rows, src + CH, (int64_t)H * RES);
     fft<RES, -1, false, true>(reg, rows + l * LS, lt, stw);
   } else {
-    const cf* src = in + ((int64_t)k1 * H + k2) * RES;
+    const cf* src = in + ((int64_t)k2 * RES + k1) * RES;
     cf nxt[E];  // W's line is loaded under the first transform
     LiveBits<RES> lb;
     if constexpr (SKIP) lb.load(livebits);
@@ -1032,7 +1032,7 @@ __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __res
 // inverse FFT along k0. Channel 0 carries kappa_0(k0); channels 1 and 2 only
 // differ by the constants kappa_1(k1), kappa_2(k2) along the line, so one
 // unscaled channel U = IFFT_k0(-i F H^) serves both (kappa_1 is applied in
-// the k1 pass, kappa_2 in the k2 pass). B[1][k1][k2][j0] (or C[1][j0][k2][k1],
+// the k1 pass, kappa_2 in the k2 pass). B[1][k2][k1][j0] (or C[1][j0][k2][k1],
 // IN_C) -> C[2][j0][k2][k1].
 template <int RES, bool IN_C>
 __device__ __forceinline__ void b_bwd_axis0(const cf* __restrict__ in, cf* __restrict__ out,
@@ -1056,7 +1056,7 @@ __device__ __forceinline__ void b_bwd_axis0(const cf* __restrict__ in, cf* __res
     load_transposed<RES, TC>(rows, in + (int64_t)k2 * RES + a0, (int64_t)H * RES);
     fft<RES, -1, false, true>(h, rows + l * LS, lt, stw);
   } else {
-    const cf* src = in + ((int64_t)k1 * H + k2) * RES;
+    const cf* src = in + ((int64_t)k2 * RES + k1) * RES;
 #pragma unroll
     for (int v = 0; v < E; ++v) h[v] = src[lt + TPL * v];
     fft<RES, -1, true, true>(h, rows + l * LS, lt, stw);
