@@ -179,8 +179,9 @@ def test_autograd_function_matches_explicit_backward(psr, dev):
 
 # ------------------------------------------------------------------ edge cases
 def test_single_point_and_one_column(psr, dev):
-    announce("edge: P=1 and a single column")
-    for res, pts in [(16, np.array([[0.3, 0.6, 0.1]])),
+    announce("edge: P=1 (16^3 to 256^3) and a single column")
+    for res, pts in [(16, np.array([[0.3, 0.6, 0.1]])), (128, np.array([[0.3, 0.6, 0.1]])),
+                     (256, np.array([[0.71, 0.2, 0.45]])),
                      (32, np.stack([np.full(400, 0.5), np.full(400, 0.25), np.linspace(0, 1, 400, endpoint=False)], 1))]:
         nrm = _rng(res).standard_normal(pts.shape)
         chi, saved = psr.forward(to_dev(pts, dev), to_dev(nrm, dev), res, 2.0)
