@@ -92,7 +92,7 @@ def stage_bytes(r: int, P: int, fp: float = 1.0, ft: float = 1.0) -> dict:
         "B5_c2r_gather": 3 * S * ft + 32 * P + 192 * P,
         "bwd_finalize": 192 * P + 16 * P + 32 * P + 24 * P,
         # plane passes (two axes per kernel; 64^3 to 256^3)
-        "P12_splat_r2c_fft_j1": 32 * P + 2 * S,        # sorted points in, v~_0 and W out
+        "P12_splat_r2c_fft_j1": 32 * P + 3 * S,        # sorted points in, v~_0, kappa_1 v~_1, kappa_2 v~_2 out
         "P45_ifft_j1_c2r_gather": S + N4 + 32 * P + 64 * P,
         "B12_cotangent_r2c_fft_j1": N4 + 32 * P + S,
         "B45_ifft_j1_c2r_gather": 2 * S * fp + 32 * P + 192 * P,  # upper bound: plane parts without points are skipped

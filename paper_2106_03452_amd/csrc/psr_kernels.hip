@@ -833,7 +833,8 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
 // l], two lines per 16-byte load) into the LDS lines rows[l * LS + pidx(n)].
 // All global loads are issued before the LDS writes; ends with a barrier.
 template <int RES, int TC>
-__device__ __forceinline__ void load_transposed(cf* rows, const cf* __restrict__ src, int64_t stride_n) {
+__device__ __forceinline__ void load_transposed(cf* rows, const cf* __restrict__ src, int64_t stride_n,
+                                                const cf* __restrict__ src2 = nullptr) {
   constexpr int BC = TC * plan_TPL(RES), LS = lstride(RES);
   constexpr int NV = RES * (TC / 2), IT = (NV + BC - 1) / BC;
   float4 buf[IT];
@@ -843,6 +844,17 @@ __device__ __forceinline__ void load_transposed(cf* rows, const cf* __restrict__
     if (e < NV) {
       const int l2 = 2 * (e % (TC / 2)), n = e / (TC / 2);
       buf[it] = *reinterpret_cast<const float4*>(src + n * stride_n + l2);
+    }
+  }
+  if (src2) {  // the sum of two channels (uniform)
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = threadIdx.x + it * BC;
+      if (e < NV) {
+        const int l2 = 2 * (e % (TC / 2)), n = e / (TC / 2);
+        const float4 y = *reinterpret_cast<const float4*>(src2 + n * stride_n + l2);
+        buf[it] = make_float4(buf[it].x + y.x, buf[it].y + y.y, buf[it].z + y.z, buf[it].w + y.w);
+      }
     }
   }
 #pragma unroll
@@ -993,7 +1005,8 @@ __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __res
     fft<RES, -1, false, true>(reg, rows + l * LS, lt, stw);
 #pragma unroll
     for (int v = 0; v < E; ++v) acc[v] = cscale(reg[v], kappa_odd(lt + TPL * v, RES));
-    load_transposed<RES, TC>(rows, src + CH, (int64_t)H * RES);
+    // W = kappa_1 v~_1 + kappa_2 v~_2, summed on load
+    load_transposed<RES, TC>(rows, src + CH, (int64_t)H * RES, src + 2 * CH);
     fft<RES, -1, false, true>(reg, rows + l * LS, lt, stw);
   } else {
     const cf* src = in + ((int64_t)k2 * RES + k1) * RES;
@@ -1398,9 +1411,11 @@ __device__ __forceinline__ cf pf_pick(const cf* rows, const cf* wr, int l, int k
   return cadd(Ee, cmul(wr[kk], Oo));
 }
 
-// P12 (MODE PF_SPLAT / PF_LOADV): channel set 0 -> v~_0, channel set 1 ->
-// W = kappa_1(k1) v~_1 + kappa_2(k2) v~_2, the two channels the j0 pass needs.
-// B12 (PF_BWDH): H^ along (j2, j1). Output C[set][j0][k2][k1].
+// P12 (MODE PF_SPLAT / PF_LOADV): one channel per workgroup, out v~_0,
+// kappa_1(k1) v~_1 and kappa_2(k2) v~_2; the j0 pass sums the last two into
+// W (the whole grid runs in one wave at 64^3 and 128^3, so equal workgroups
+// beat one doing both W channels). B12 (PF_BWDH): H^ along (j2, j1). Output
+// C[set][j0][k2][k1].
 template <int RES, int MODE>
 __device__ __forceinline__ void b_plane_fwd(const PointRec* __restrict__ sorted, const int* __restrict__ off,
                                             const float* __restrict__ gin, BwdScalars* __restrict__ bs,
@@ -1409,7 +1424,7 @@ __device__ __forceinline__ void b_plane_fwd(const PointRec* __restrict__ sorted,
   using PL = Plane<RES>;
   constexpr int M = PL::M, H = PL::H, KP = PL::KP, NCOL = PL::NCOL, TPL = PL::TPL, RC = PL::RC;
   constexpr int NCHUNK = PL::NCHUNK, LSC = PL::LSC, BLOCK = PL::BLOCK;
-  constexpr int NSET = MODE == PF_BWDH ? 1 : 2;
+  constexpr int NSET = MODE == PF_BWDH ? 1 : 3;
   constexpr int VPC = 16 / NCHUNK;  // register elements filled per chunk
   constexpr int64_t CH = (int64_t)H * RES * RES;
   __shared__ cf buf[PL::SLOTS];
@@ -1437,10 +1452,9 @@ __device__ __forceinline__ void b_plane_fwd(const PointRec* __restrict__ sorted,
   }
   float3 sqa = make_float3(1.0f, 0.0f, 1.0f);
   if constexpr (MODE == PF_BWDH) sqa = bwd_scalars<BLOCK>(bpart, bwd_reduce_blocks<RES>(), hdr, bs, bid == 0);
-  cf reg[16], acc[16];
-  const int npass = set == 1 ? 2 : 1;
-  for (int pass = 0; pass < npass; ++pass) {
-    const int ch = set == 0 ? 0 : 2 - pass;  // set 1: channel 2, then channel 1
+  cf reg[16];
+  {
+    const int ch = set;
 #pragma unroll 1
     for (int q = 0; q < NCHUNK; ++q) {
       const int a0 = q * RC;
@@ -1456,16 +1470,16 @@ __device__ __forceinline__ void b_plane_fwd(const PointRec* __restrict__ sorted,
       __syncthreads();  // the rows are overwritten next
     }
     fft<RES, -1, true, true>(reg, buf + col * LSC, lt, ctw);
-    if (set == 1 && pass == 0) {
-      // kappa_2(k2) v~_2; zero in the packed column (kappa_2^odd vanishes at k2 = 0 and M)
-      const float k2f = kk == 0 ? 0.0f : kappa_odd(kk, RES);
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[v] = cscale(reg[v], k2f);
-    }
   }
   if (set == 1 && kk != 0) {
 #pragma unroll
-    for (int v = 0; v < 16; ++v) reg[v] = cadd(cscale(reg[v], kappa_odd(lt + TPL * v, RES)), acc[v]);
+    for (int v = 0; v < 16; ++v) reg[v] = cscale(reg[v], kappa_odd(lt + TPL * v, RES));
+  }
+  if (set == 2) {
+    // kappa_2(k2); zero in the packed column (kappa_2^odd vanishes at k2 = 0 and M)
+    const float k2f = kk == 0 ? 0.0f : kappa_odd(kk, RES);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) reg[v] = cscale(reg[v], k2f);
   }
   // unpack the packed column with its mirror k1 -> -k1:
   // F_0 = (P(k) + P*(-k)) / 2, F_M = (P(k) - P*(-k)) / (2i)
@@ -2017,7 +2031,7 @@ static int seq_forward(Exec& x, const JobArg* J, int n) {
   x.end(STAGE_BIN);
   if constexpr (use_plane(RES)) {
     x.begin(STAGE_P12);
-    rc |= launch<MAXJ>(x, k_plane_fwd<RES, PF_SPLAT, MAXJ>, Plane<RES>::BLOCK, J, n, c(RES * Plane<RES>::KP * 2));
+    rc |= launch<MAXJ>(x, k_plane_fwd<RES, PF_SPLAT, MAXJ>, Plane<RES>::BLOCK, J, n, c(RES * Plane<RES>::KP * 3));
     x.end(STAGE_P12);
   } else {
     x.begin(STAGE_P1);
@@ -2116,7 +2130,7 @@ static int debug_spectral_res(Exec& x, const JobArg& job) {
   auto c = [](int v) { return [v](const JobArg&) { return v; }; };
   int rc = 0;
   if constexpr (use_plane(RES)) {
-    rc |= launch<1>(x, k_plane_fwd<RES, PF_LOADV, 1>, Plane<RES>::BLOCK, &job, 1, c(RES * Plane<RES>::KP * 2));
+    rc |= launch<1>(x, k_plane_fwd<RES, PF_LOADV, 1>, Plane<RES>::BLOCK, &job, 1, c(RES * Plane<RES>::KP * 3));
   } else {
     rc |= launch<1>(x, k_splat_r2c<RES, MODE_LOADV, 1>, G::BR, &job, 1, c(3 * G::rows));
     rc |= launch<1>(x, k_axis1_fwd<RES, true, false, 1>, G::BC, &job, 1, c(2 * G::cols));
