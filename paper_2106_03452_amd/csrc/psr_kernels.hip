@@ -191,26 +191,24 @@ __device__ __forceinline__ void for_recs(const Recs<K>& r, const PointRec* __res
 }
 
 // Fixed-point splat. LDS float atomics are several times slower than integer
-// ones on gfx950, so the splat of a span of rows accumulates integers: each
-// corner adds rintf(w * value * 2^S), with 2^S * T * maxabs <= 2^30, where T
-// counts the points of the span and maxabs bounds their |value|. A point adds
-// at most |value| to a vertex, once, so every partial sum stays below
-// 2^30 + T / 2 < 2^31; the step 2^-S is below 2 T maxabs / 2^30. Integer sums
-// do not depend on the order of the adds: the splat is bitwise reproducible.
-// Spans of more than kFixedMaxPoints points, where one point's contribution
-// would be resolved to fewer than 2^30 / T = 2^14 steps of maxabs, keep LDS
-// float atomics.
-constexpr int kFixedMaxPoints = 1 << 16;
-
-// Returns 2^S for T = cnt points bounded by maxabs and sets inv = 2^-S (both
-// built from exponent bits).
-__device__ __forceinline__ float splat_scale(int cnt, float maxabs, float& inv) {
-  const float b = (float)cnt * maxabs;
+// ones on gfx950, and their result depends on the order of the adds, so the
+// splat accumulates integers: each corner contribution w * value becomes
+// rintf(w * value * 2^S) with 2^S * maxabs <= 2^30, where maxabs bounds the
+// |value| of the span's points. Every contribution then fits in 31 bits and
+// is added to a 64-bit LDS accumulator; at most 2^30 points (the library's
+// limit) keep any partial sum below 2^60. The rounding error of one
+// contribution is at most 2^-S / 2 <= maxabs * 2^-30, independent of how
+// many points share the span or how their contributions cancel (opposite
+// normals of a thin wall in one cell). Integer sums do not depend on the
+// order of the adds: the splat is bitwise reproducible.
+//
+// Returns 2^S for maxabs and sets inv = 2^-S (both built from exponent bits).
+__device__ __forceinline__ float splat_scale(float maxabs, float& inv) {
   int S = 0;
-  if (b > 0.0f) {
-    // b < 2^e with e = biased exponent - 126 (also for subnormal b); an
-    // infinite b (absurd normals) takes the smallest scale
-    const int e = ((__float_as_int(b) >> 23) & 0xff) - 126;
+  if (maxabs > 0.0f) {
+    // maxabs < 2^e with e = biased exponent - 126 (also for subnormal
+    // maxabs); an infinite maxabs (absurd normals) takes the smallest scale
+    const int e = ((__float_as_int(maxabs) >> 23) & 0xff) - 126;
     S = 30 - e;
     S = S > 126 ? 126 : (S < -126 || e > 128 ? -126 : S);
   }
@@ -552,10 +550,9 @@ __device__ __forceinline__ float3 bwd_scalars(const double2* __restrict__ blockp
 template <int RES, int NROWS, int BLOCK, int KIND>
 __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__ sorted, const Ranges& R,
                                           const float* __restrict__ gin, float3 sqa, int j0, int a0, int ch) {
-  constexpr int M = RES / 2, LS = row_ls(M);
+  constexpr int M = RES / 2;
   constexpr int64_t N3 = (int64_t)RES * RES * RES;
   const int t = threadIdx.x;
-  float* const rf = reinterpret_cast<float*>(rows);
   // the NROWS rows are one contiguous run of NROWS * RES floats
   constexpr int NV = NROWS * M / 2;  // float4 = two complex slots
   constexpr int IT = (NV + BLOCK - 1) / BLOCK;
@@ -582,14 +579,17 @@ __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__
       }
     }
   } else if constexpr (KIND != 2) {
-    // splat of normal component ch (or of unit weights: W in the backward),
-    // in fixed point unless the span is very dense; then back to floats, and
-    // in the backward H = s G - Q delta_0 + alpha W
+    // splat of normal component ch (or of unit weights: W in the backward)
+    // in 64-bit fixed point, then back to floats, and in the backward
+    // H = s G - Q delta_0 + alpha W. A complex LDS slot (8 bytes) holds two
+    // samples as floats but one as a 64-bit integer, so the samples are
+    // accumulated in two rounds in place: even samples (the real parts),
+    // then odd samples; the even sums wait in registers meanwhile.
     __shared__ float wmax[(BLOCK + 63) / 64];
     constexpr int KR = 4;
     Recs<KR> recs;
     fetch_recs<KR, BLOCK>(recs, sorted, R, t);
-    int* const ri = reinterpret_cast<int*>(rows);
+    unsigned long long* const r64 = reinterpret_cast<unsigned long long*>(rows);
     float4 gbuf[KIND == 1 ? IT : 1];
     if constexpr (KIND == 1) {
       const float4* g4 = reinterpret_cast<const float4*>(gin + ((int64_t)j0 * RES + a0) * RES);
@@ -599,7 +599,18 @@ __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__
         if (e < NV) gbuf[it] = g4[e];
       }
     }
-    for (int e = t; e < NROWS * LS * 2; e += BLOCK) ri[e] = 0;  // integer and float zero alike
+    // each thread owns the two slots (l, mm), (l, mm + 1) of its float4s:
+    // every slot the splat touches has one owner, which zeroes it before
+    // each round and converts it after
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * BLOCK;
+      if (e < NV) {
+        const int mm = (2 * e) % M, l = (2 * e) / M;
+        r64[rpos<M>(l, mm)] = 0ull;
+        r64[rpos<M>(l, mm + 1)] = 0ull;
+      }
+    }
     float m = 1.0f;
     if constexpr (KIND == 0) {
       m = 0.0f;
@@ -609,67 +620,63 @@ __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__
     }
     wave_max_store<BLOCK>(wmax, m);
     __syncthreads();
-    const bool fixedp = R.total <= kFixedMaxPoints;  // uniform over the workgroup
     float inv = 1.0f;
-    const float sc = fixedp ? splat_scale(R.total, block_max<BLOCK>(wmax), inv) : 1.0f;
-    for_recs<KR, BLOCK>(recs, sorted, R, t, [&](const float4& p0, const float4& p1, int64_t) {
-      const uint32_t bb = __float_as_uint(p0.w);
-      const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
-      float val;
-      if constexpr (KIND == 1) val = 1.0f;
-      else val = ch == 0 ? p1.x : (ch == 1 ? p1.y : p1.z);
+    const float sc = splat_scale(block_max<BLOCK>(wmax), inv);
+    float2 even[IT];  // the finished even samples (l, 2 mm) and (l, 2 mm + 2) of each owned float4
+    const float alpha = KIND == 1 ? sqa.z : 1.0f;
+#pragma unroll 1
+    for (int par = 0; par < 2; ++par) {
+      for_recs<KR, BLOCK>(recs, sorted, R, t, [&](const float4& p0, const float4& p1, int64_t) {
+        const uint32_t bb = __float_as_uint(p0.w);
+        const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
+        float val;
+        if constexpr (KIND == 1) val = 1.0f;
+        else val = ch == 0 ? p1.x : (ch == 1 ? p1.y : p1.z);
+        // the corner along j2 whose sample index has this round's parity
+        // (r is even, so the wrap keeps the parity)
+        const int o2 = (b2 & 1) ^ par;
+        const int nn = (b2 + o2) & (RES - 1);
+        const float w2 = o2 ? p0.z : 1.0f - p0.z;
 #pragma unroll
-      for (int o0 = 0; o0 < 2; ++o0) {
-        if (((b0 + o0) & (RES - 1)) != j0) continue;
-        const float w0 = o0 ? p0.x : 1.0f - p0.x;
+        for (int o0 = 0; o0 < 2; ++o0) {
+          if (((b0 + o0) & (RES - 1)) != j0) continue;
+          const float w0 = o0 ? p0.x : 1.0f - p0.x;
 #pragma unroll
-        for (int o1 = 0; o1 < 2; ++o1) {
-          const int l = (b1 + o1 - a0) & (RES - 1);
-          if (l >= NROWS) continue;
-          const float w01 = w0 * (o1 ? p0.y : 1.0f - p0.y) * val;
-#pragma unroll
-          for (int o2 = 0; o2 < 2; ++o2) {
-            const int nn = (b2 + o2) & (RES - 1);
-            const float w = w01 * (o2 ? p0.z : 1.0f - p0.z);
-            const int slot = 2 * rpos<M>(l, nn >> 1) + (nn & 1);
-            if (fixedp) atomicAdd(&ri[slot], (int)rintf(w * sc));
-            else atomicAdd(&rf[slot], w);
+          for (int o1 = 0; o1 < 2; ++o1) {
+            const int l = (b1 + o1 - a0) & (RES - 1);
+            if (l >= NROWS) continue;
+            // w2 first: every product depends on the round, so nothing of it
+            // is hoisted out of the round loop into registers
+            const float w = ((w2 * w0) * (o1 ? p0.y : 1.0f - p0.y)) * val;
+            atomicAdd(&r64[rpos<M>(l, nn >> 1)], (unsigned long long)(long long)(int)rintf(w * sc));
           }
         }
-      }
-    });
-    if (KIND == 1 || fixedp) {
+      });
       __syncthreads();
-      float sg = 0.0f, q = 0.0f, alpha = 1.0f;
-      if constexpr (KIND == 1) {
-        sg = sqa.x;
-        q = sqa.y;
-        alpha = sqa.z;
-      }
-      const float fac = inv * alpha;
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
         const int e = t + it * BLOCK;
         if (e < NV) {
           const int mm = (2 * e) % M, l = (2 * e) / M;
-          const int i0 = 2 * rpos<M>(l, mm), i1 = 2 * rpos<M>(l, mm + 1);
-          float4 v;
-          if (fixedp) v = make_float4((float)ri[i0], (float)ri[i0 + 1], (float)ri[i1], (float)ri[i1 + 1]);
-          else v = make_float4(rf[i0], rf[i0 + 1], rf[i1], rf[i1 + 1]);
-          v = make_float4(v.x * fac, v.y * fac, v.z * fac, v.w * fac);
+          const int i0 = rpos<M>(l, mm), i1 = rpos<M>(l, mm + 1);
+          float x0 = (float)(long long)r64[i0] * inv, x1 = (float)(long long)r64[i1] * inv;
           if constexpr (KIND == 1) {
-            v.x += sg * gbuf[it].x;
-            v.y += sg * gbuf[it].y;
-            v.z += sg * gbuf[it].z;
-            v.w += sg * gbuf[it].w;
-            if (j0 == 0 && a0 + l == 0 && mm == 0) v.x -= q;
+            // H = s G + alpha W - Q delta_0
+            x0 = alpha * x0 + sqa.x * (par ? gbuf[it].y : gbuf[it].x);
+            x1 = alpha * x1 + sqa.x * (par ? gbuf[it].w : gbuf[it].z);
+            if (par == 0 && j0 == 0 && a0 + l == 0 && mm == 0) x0 -= sqa.y;
           }
-          rf[i0] = v.x;
-          rf[i0 + 1] = v.y;
-          rf[i1] = v.z;
-          rf[i1 + 1] = v.w;
+          if (par == 0) {
+            even[it] = make_float2(x0, x1);
+            r64[i0] = 0ull;
+            r64[i1] = 0ull;
+          } else {
+            rows[i0] = cf{even[it].x, x0};
+            rows[i1] = cf{even[it].y, x1};
+          }
         }
       }
+      if (par == 0) __syncthreads();  // the odd round's adds reach slots other threads own
     }
   }
   __syncthreads();
@@ -754,7 +761,7 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
   constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_block(RES);
   constexpr int TPL = plan_TPL(M), E = plan_E(M), LS = row_ls(M);
   constexpr int64_t N3 = (int64_t)RES * RES * RES;
-  __shared__ cf rows[TR * LS];
+  __shared__ __align__(16) cf rows[TR * LS];
   __shared__ cf stw[M];      // FFT table of length M
   __shared__ cf rtw[M + 1];  // W_RES^k, k in [0, M], for the r2c post-processing
   if constexpr (MODE != MODE_VOUT) {
@@ -1191,7 +1198,7 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
                                                                const cf* __restrict__ tw, int bid) {
   constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_block(RES);
   constexpr int TPL = plan_TPL(M), E = plan_E(M), LS = row_ls(M);
-  __shared__ cf rows[TR * LS];
+  __shared__ __align__(16) cf rows[TR * LS];
   __shared__ cf stw[M];      // FFT table of length M
   __shared__ cf rtw[M + 1];  // W_RES^k, k in [0, M], for the c2r pre-processing
   stage_table<BR>(stw, tw + M, M);
@@ -1427,7 +1434,7 @@ __device__ __forceinline__ void b_plane_fwd(const PointRec* __restrict__ sorted,
   constexpr int NSET = MODE == PF_BWDH ? 1 : 3;
   constexpr int VPC = 16 / NCHUNK;  // register elements filled per chunk
   constexpr int64_t CH = (int64_t)H * RES * RES;
-  __shared__ cf buf[PL::SLOTS];
+  __shared__ __align__(16) cf buf[PL::SLOTS];
   __shared__ cf stw[M];    // FFT table of length M (rows)
   __shared__ cf ctw[RES];  // FFT table of length RES (columns); its first M + 1 entries are W_r^k for the r2c
   stage_table<BLOCK>(stw, tw + M, M);
@@ -1510,6 +1517,33 @@ __device__ __forceinline__ void b_plane_fwd(const PointRec* __restrict__ sorted,
   }
 }
 
+// Splat test hook of the plane passes: the rows that P12 splats for plane
+// j0 and channel c (the same fill_rows instantiation and spans), written to
+// v_c[j0] instead of being transformed.
+template <int RES>
+__device__ __forceinline__ void b_plane_splat_dbg(const PointRec* __restrict__ sorted, const int* __restrict__ off,
+                                                  float* __restrict__ vout, int bid) {
+  using PL = Plane<RES>;
+  constexpr int M = PL::M, RC = PL::RC, BLOCK = PL::BLOCK;
+  constexpr int64_t N3 = (int64_t)RES * RES * RES;
+  __shared__ __align__(16) cf buf[PL::SLOTS];
+  const int j0 = bid / 3, c = bid % 3, t = threadIdx.x;
+  const float* rf = reinterpret_cast<const float*>(buf);
+#pragma unroll 1
+  for (int q = 0; q < PL::NCHUNK; ++q) {
+    const int a0 = q * RC;
+    const Ranges R = span_ranges<RES, RC>(off, j0, a0);
+    if (R.total > 0) fill_rows<RES, RC, BLOCK, PF_SPLAT>(buf, sorted, R, nullptr, make_float3(1.0f, 0.0f, 1.0f),
+                                                         j0, a0, c);
+    for (int e = t; e < RC * RES; e += BLOCK) {
+      const int nn = e % RES, l = e / RES;
+      vout[c * N3 + ((int64_t)j0 * RES + a0 + l) * RES + nn] =
+          R.total > 0 ? rf[2 * rpos<M>(l, nn >> 1) + (nn & 1)] : 0.0f;
+    }
+    __syncthreads();
+  }
+}
+
 enum { PI_FWD = 0, PI_BWD = 1, PI_DBG = 2 };
 
 // P45 (PI_FWD): chi' rows and the gather partials at the points (slot-major,
@@ -1529,7 +1563,7 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
   constexpr int NCH = MODE == PI_BWD ? 3 : 1;
   constexpr int VK = 16 / KP;  // elements kept per round: the part's rows of the column
   constexpr int64_t CH = (int64_t)H * RES * RES;
-  __shared__ cf buf[PL::SLOTS];
+  __shared__ __align__(16) cf buf[PL::SLOTS];
   __shared__ cf stw[M];
   __shared__ cf ctw[RES];
   stage_table<BLOCK>(stw, tw + M, M);
@@ -1946,6 +1980,13 @@ void k_plane_inv(const Batch<MAXJ> B) {
 }
 
 template <int RES, int MAXJ>
+__global__ __launch_bounds__(Plane<RES>::BLOCK) __attribute__((amdgpu_waves_per_eu(Plane<RES>::WPE)))
+void k_plane_splat_dbg(const Batch<MAXJ> B) {
+  PSR_JOB(RES);
+  b_plane_splat_dbg<RES>(sv.sorted, sv.off, J.aux_out, bid);
+}
+
+template <int RES, int MAXJ>
 __global__ __launch_bounds__(256) void k_fwd_point_reduce(const Batch<MAXJ> B) {
   PSR_JOB(RES);
   b_fwd_point_reduce(w.part, J.P, sv.gradf, w.blockpart, bid, nbl);
@@ -2158,7 +2199,11 @@ static int debug_splat_res(Exec& x, const JobArg& job) {
     rc |= launch<1>(x, k_scan<RES, 1>, 1024, &job, 1, c(1));
     rc |= launch<1>(x, k_scatter<RES, 1>, 256, &job, 1, [](const JobArg& a) { return nblk(a.P, 256); });
   }
-  rc |= launch<1>(x, k_splat_r2c<RES, MODE_VOUT, 1>, G::BR, &job, 1, c(3 * G::rows));
+  // the splat of the production path: plane passes at 64 and 128, row passes elsewhere
+  if constexpr (use_plane(RES))
+    rc |= launch<1>(x, k_plane_splat_dbg<RES, 1>, Plane<RES>::BLOCK, &job, 1, c(3 * RES));
+  else
+    rc |= launch<1>(x, k_splat_r2c<RES, MODE_VOUT, 1>, G::BR, &job, 1, c(3 * G::rows));
   return rc ? -4 : 0;
 }
 

@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "rng_for", "sphere", "torus", "superellipsoid", "random_rotation",
     "Shape", "config_c1", "config_c2", "config_c2_outliers", "config_c3", "config_c4", "config_c5",
-    "random_shape", "tiny_case", "loss_gradient",
+    "random_shape", "tiny_case", "loss_gradient", "thin_plate",
 ]
 
 
@@ -258,6 +258,22 @@ def config_c5(seed: int = 4, n_requests: int = 2000):
         reqs.append((random_shape(rng, res, P), bwd))
     arrivals_unit = rng.exponential(1.0, n_requests)
     return reqs, arrivals_unit
+
+
+def thin_plate(seed: int, P: int, res: int, half_thickness: float = 0.006, table=(256, 512)) -> Shape:
+    """A thin closed plate: P points by area on a flat superellipsoid with axes
+    (half_thickness, 0.3, 0.3) along grid axes (0, 1, 2) (exponents 0.5 across
+    the plate, 1.0 round its rim), centred on the middle of cell res/2 along
+    axis 0, so at 64^3 every point sits in one floor plane. Its two faces carry
+    opposite normals a fraction of a cell apart: they cancel inside the
+    splat's cells (the case that stresses the splat's summation precision)."""
+    rng = rng_for(seed)
+    centre = ((res // 2 + 0.5) / res, 0.5, 0.5)
+    # generated thin along z (the superellipsoid's eta axis), then axes rolled so z -> axis 0
+    p, n = superellipsoid(rng, P, (0.0, 0.0, 0.0), (0.3, 0.3, half_thickness), 0.5, 1.0, table)
+    p = p[:, [2, 0, 1]] + np.asarray(centre)
+    n = n[:, [2, 0, 1]]
+    return Shape(res, 2.0, _f32(p), _f32(n), kind="thin_plate", meta=dict(half_thickness=half_thickness))
 
 
 def loss_gradient(res: int, seed: int) -> np.ndarray:
