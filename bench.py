@@ -11,9 +11,14 @@ Default workload: 256^3 grid, 100,000 points on a random superellipsoid
 the loss is mean((chi - chi_t)^2) with chi_t from the clean normals.
 
 Printed: ONE JSON line with solves/s, the dominant kernel's roofline
-(algorithmic bytes / HIP-event duration, against 8 TB/s), the whole-step
-roofline, secondary 128^3 and forward-only rates, and the FP64 oracle timed on
-the host's cores on one solve of the same workload.
+(algorithmic bytes / HIP-event duration, against 8 TB/s), two whole-step
+rates (dense-equivalent: B_stage = 128 r^3 + 72 P over the step time, which
+counts planes and row tiles the kernels skip; skip-aware: the bytes of the
+stages actually run), secondary lines (128^3 fwd+bwd and forward only, 256^3
+forward only, 256^3 with half the points uniform outliers so that nothing can
+be skipped, 32^3 forward only, the 64-shape batch, a compact serving run with
+p50/p99 latency), and the FP64 oracle timed on one host core on the headline
+workload together with the GPU's error against that oracle run.
 """
 from __future__ import annotations
 
@@ -78,7 +83,9 @@ def stage_bytes(r: int, P: int, fp: float = 1.0, ft: float = 1.0) -> dict:
         "bin": 24 * P + 32 * P * 2 + 8 * P,
         "P1_splat_r2c": 32 * P + 3 * S * ft,           # sorted points in, 3 half-spectra of touched row tiles out
         "P2_fft_j1": 3 * S * ft + 2 * S * fp,          # touched tile segments of 3 channels in, v~_0 and merged W of live planes out
-        "P3_fft_j0_spectral_ifft_j0": 2 * S * fp + S,  # live planes of the 2 in, chi~ (after the k0 inverse) out
+        # live planes of the 2 in, chi~ (after the k0 inverse) out; at 64-128 the plane pass hands over 3 channels
+        # (v~_0, kappa_1 v~_1, kappa_2 v~_2), read whole
+        "P3_fft_j0_spectral_ifft_j0": (3 * S if 64 <= r <= 128 else 2 * S * fp) + S,
         "P4_ifft_j1": 2 * S,
         "P5_c2r_gather": S + N4 + 32 * P + 64 * P,     # chi' written, gather partials
         "fwd_reduce": 64 * P + 16 * P,
@@ -97,6 +104,26 @@ def stage_bytes(r: int, P: int, fp: float = 1.0, ft: float = 1.0) -> dict:
         "B12_cotangent_r2c_fft_j1": N4 + 32 * P + S,
         "B45_ifft_j1_c2r_gather": 2 * S * fp + 32 * P + 192 * P,  # upper bound: plane parts without points are skipped
     }
+
+
+def path_stages(r: int, backward: bool = True) -> list:
+    """The stages one solve runs at grid size r (plane passes at 64-128, the
+    plane inverse pass also at 256, two-pass row/column kernels elsewhere)."""
+    plane, p45 = 64 <= r <= 128, 64 <= r <= 256
+    f = ["bin"] + (["P12_splat_r2c_fft_j1"] if plane else ["P1_splat_r2c", "P2_fft_j1"])
+    f += ["P3_fft_j0_spectral_ifft_j0"] + (["P45_ifft_j1_c2r_gather"] if p45 else ["P4_ifft_j1", "P5_c2r_gather"])
+    f += ["fwd_reduce", "normalize"]
+    b = ["bwd_reduce", "B12_cotangent_r2c_fft_j1"] if plane else ["B1a_reduce_r2c", "B1_cotangent_r2c", "B2_fft_j1"]
+    b += ["B3_fft_j0_conjop_ifft_j0"] + (["B45_ifft_j1_c2r_gather"] if plane else ["B4_ifft_j1", "B5_c2r_gather"])
+    b += ["bwd_finalize"]
+    return f + (b if backward else [])
+
+
+def skip_aware_bytes(r: int, P: int, fp: float, ft: float, backward: bool = True) -> float:
+    """Algorithmic bytes of the stages a solve actually runs, with the
+    point-free planes and row tiles that the kernels skip left out."""
+    sb = stage_bytes(r, P, fp, ft)
+    return float(sum(sb[st] for st in path_stages(r, backward)))
 
 
 def b_stage(r: int, P: int) -> int:
@@ -221,23 +248,42 @@ for _ in range(3):
     G = 2.0 * (chi - chi_t) / chi.size
     dc, dn = oracle.backward(aux, G)
     secs.append(time.perf_counter() - t0)
+np.savez({out!r}, chi=chi, dc=dc, dn=dn)
 print(json.dumps(dict(seconds=sorted(secs)[1])))
 """
 
 
-def cpu_baseline():
+def cpu_baseline(gpu_result=None):
+    """The FP64 oracle timed on one host core over three full solves of the
+    headline workload; with ``gpu_result`` = (chi, dpoints, dnormals) of the
+    GPU on the same workload, also the GPU's error against this oracle run
+    (e_chi = max|dchi| / max|chi|, e_g = relative L2 per gradient)."""
+    import tempfile
+    import numpy as np
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
                NUMEXPR_NUM_THREADS="1")
-    out = subprocess.run([sys.executable, "-c", CPU_SNIPPET.format(root=ROOT)], env=env, capture_output=True,
-                         text=True, timeout=900)
-    if out.returncode != 0:
-        sys.stderr.write(out.stderr[-2000:])
-        return None
-    sec = json.loads(out.stdout.strip().splitlines()[-1])["seconds"]
-    return {"value": round(1.0 / sec, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"three full forward+backward solves of the same 256^3 / 100k-point workload, median "
-                      f"{sec:.1f} s (FP64 NumPy oracle, single thread; the loss target chi_t is computed "
-                      f"outside the timed samples)"}
+    with tempfile.TemporaryDirectory() as td:
+        npz = os.path.join(td, "oracle_c3.npz")
+        out = subprocess.run([sys.executable, "-c", CPU_SNIPPET.format(root=ROOT, out=npz)], env=env,
+                             capture_output=True, text=True, timeout=900)
+        if out.returncode != 0:
+            sys.stderr.write(out.stderr[-2000:])
+            return None
+        sec = json.loads(out.stdout.strip().splitlines()[-1])["seconds"]
+        res = {"value": round(1.0 / sec, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"three full forward+backward solves of the same 256^3 / 100k-point workload, median "
+                         f"{sec:.1f} s (FP64 NumPy oracle, single thread; the loss target chi_t is computed "
+                         f"outside the timed samples)"}
+        if gpu_result is not None:
+            ref = np.load(npz)
+            chi, dp, dn = (np.asarray(a, dtype=np.float64) for a in gpu_result)
+            rel2 = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            res["parity"] = {"e_chi": float(np.abs(chi - ref["chi"]).max() / np.abs(ref["chi"]).max()),
+                             "e_dpoints": rel2(dp, ref["dc"]), "e_dnormals": rel2(dn, ref["dn"]),
+                             "bars": {"e_chi": 1e-5, "e_dpoints": 1e-4, "e_dnormals": 1e-4},
+                             "note": "GPU forward+backward of the timed workload (FP32 bulk, FP64 reductions; "
+                                     "each side forms its own loss gradient) against this FP64 oracle run"}
+    return res
 
 
 def step_times(step, reps, torch, scrub=None):
@@ -262,10 +308,13 @@ def prepare(shape, dev, torch, F):
     pts = torch.from_numpy(shape.points).to(dev)
     nrm = torch.from_numpy(shape.normals).to(dev)
     r, P = shape.res, shape.P
-    chi_t, _ = F.forward(torch.from_numpy(shape.points_clean).to(dev), torch.from_numpy(shape.normals_clean).to(dev),
-                         r, shape.sigma)
     chi, saved = F.forward(pts, nrm, r, shape.sigma)
-    G = (2.0 * (chi - chi_t) / chi.numel()).contiguous()
+    if shape.points_clean is not None:
+        chi_t, _ = F.forward(torch.from_numpy(shape.points_clean).to(dev),
+                             torch.from_numpy(shape.normals_clean).to(dev), r, shape.sigma)
+        G = (2.0 * (chi - chi_t) / chi.numel()).contiguous()
+    else:  # forward-only workloads: the backward is never run
+        G = torch.zeros_like(chi)
     from paper_2106_03452_amd import _lib
     ws = torch.empty(_lib.workspace_bytes(r, P), dtype=torch.uint8, device=dev)
     dp = torch.empty((P, 3), dtype=torch.float32, device=dev)
@@ -335,18 +384,18 @@ def batch_c4(dev, torch, steps=10, warmup=3):
             "step_roofline_frac": round(total_bytes / t_b / 1e9 / HBM_PEAK_GBS, 4)}
 
 
-def serve_mode(dev, torch, n_requests):
+def serve_mode(dev, torch, n_requests, levels=(0.5, 0.8, 1.0, 1.5)):
     """Poisson request stream (seed 4): res in {64,128,256}, P log-uniform in
     [3e3, 2e5], 50/50 forward vs forward+backward. lambda_seq = throughput of
-    sequential plain solves over the stream; then, at QPS = {0.5,0.8,1.0,1.5}
-    x lambda_seq, the continuous-batching engine and the sequential baseline
+    sequential plain solves over the stream; then, at QPS = level x
+    lambda_seq, the continuous-batching engine and the sequential baseline
     serve the same arrivals; p50/p99 latency skip the first 100 requests."""
     import numpy as np
     import psr_synth as S
     from paper_2106_03452_amd import _lib
     from paper_2106_03452_amd.serve import Engine, GpuBackend, Request, SequentialBaseline, drive, latency_stats
     print(f"serve: generating {n_requests} requests", file=sys.stderr, flush=True)
-    reqs_spec, arrivals_unit = S.config_c5(n_requests=n_requests)
+    reqs_spec, arrivals_unit = S.config_c5(n_requests=n_requests, workers=min(16, os.cpu_count() or 1))
     classes = {64: 200000, 128: 200000, 256: 200000}
     data = []
     rng = np.random.Generator(np.random.PCG64(44))
@@ -373,7 +422,7 @@ def serve_mode(dev, torch, n_requests):
                        "Poisson arrivals (seed 4)",
            "lambda_seq_solves_per_s": round(lam, 1), "levels": []}
     print(f"serve: lambda_seq = {lam:.1f} solves/s", file=sys.stderr, flush=True)
-    for f in (0.5, 0.8, 1.0, 1.5):
+    for f in levels:
         print(f"serve: level {f}", file=sys.stderr, flush=True)
         qps = f * lam
         arr = np.cumsum(arrivals_unit[:len(data)]) / qps
@@ -412,6 +461,9 @@ def main():
     ap.add_argument("--mode", choices=["solve", "serve"], default="solve",
                     help="solve: the fwd+bwd throughput line (default); serve: the request-stream measurement")
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: requests per QPS level")
+    ap.add_argument("--serve-requests", type=int, default=600,
+                    help="requests of the compact serving leg of the default run (levels 1.0 and 1.5 x lambda_seq)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the compact serving leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (scale reference for HBM counters)")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -485,15 +537,26 @@ def main():
             "kernel": dom, "algorithmic_bytes_per_launch": round(sb[dom]), "avg_launch_ms": round(dom_ms, 5),
             "live_plane_fraction": round(fp, 4), "live_tile_fraction": round(ft, 4)}
     step_bytes = b_stage(r, P)
-    step_roof = {"bytes": step_bytes, "achieved_GBs": round(step_bytes / (ms * 1e-3) / 1e9, 1),
-                 "frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                 "model": "B_stage = 128 r^3 + 72 P (fwd+bwd)"}
+    rate = lambda nbytes, ms_: nbytes / (ms_ * 1e-3) / 1e9
+    # B_stage counts every plane and row tile; the kernels skip the point-free
+    # ones, so this is a dense-equivalent rate, not bytes moved over HBM
+    step_dense = {"bytes": step_bytes, "achieved_GBs": round(rate(step_bytes, ms), 1),
+                  "frac": round(rate(step_bytes, ms) / HBM_PEAK_GBS, 4),
+                  "model": "B_stage = 128 r^3 + 72 P (fwd+bwd), every plane and row tile counted: a "
+                           "dense-equivalent rate (the kernels skip point-free planes and tiles)",
+                  "B_min": 56 * r ** 3 + 72 * P,
+                  "B_min_frac": round(rate(56 * r ** 3 + 72 * P, ms) / HBM_PEAK_GBS, 4)}
+    sk = skip_aware_bytes(r, P, fp, ft)
+    step_skip = {"bytes": round(sk), "achieved_GBs": round(rate(sk, ms), 1),
+                 "frac": round(rate(sk, ms) / HBM_PEAK_GBS, 4),
+                 "model": "sum of the algorithmic bytes of the stages run, point-free planes and row tiles left out",
+                 "live_plane_fraction": round(fp, 4), "live_tile_fraction": round(ft, 4)}
     breakdown = {k: round(v, 4) for k, v in sorted(per_launch.items(), key=lambda kv: -kv[1])}
-    step_roof["B_min"] = 56 * r ** 3 + 72 * P
-    step_roof["B_min_frac"] = round(step_roof["B_min"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     tr = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic_c3_256.json"))) if traffic is not None else None
     if tr is not None:
-        step_roof["counter_bytes_large_kernels"] = sum(v["hbm_bytes_per_launch"] for v in tr["stages"].values())
+        cb = sum(v["hbm_bytes_per_launch"] for v in tr["stages"].values())
+        step_skip["counter_bytes_large_kernels"] = cb
+        step_skip["counter_frac_large_kernels"] = round(rate(cb, ms) / HBM_PEAK_GBS, 4)
     # warm (back-to-back) and cold (caches scrubbed by a 512 MiB write) repetitions
     scrub = torch.empty(1 << 27, dtype=torch.float32, device=dev)
     timing = {"warm": step_times(step, 50, torch), "cold": step_times(step, 50, torch, scrub)}
@@ -522,9 +585,41 @@ def main():
         secondary["fwd_only_128"] = {"solves_per_s": round(args.steps * 3 / d3, 2),
                                      "ms": round(d3 / (args.steps * 3) * 1e3, 4), "paper_gtx1080ti_ms": 12.0}
         del b2
+        # the dense worst case: half of the C3 cloud replaced by uniform outliers,
+        # so every plane and row tile is live and nothing can be skipped
+        sh3 = S.config_c3_outliers()
+        b3 = prepare(sh3, dev, torch, F)
+        s3 = make_step(b3, ctx)
+        d3 = timed(s3, args.steps, args.warmup, torch)
+        ms3 = d3 / args.steps * 1e3
+        fp3, ft3 = live_fractions(sh3.points, 256)
+        sk3 = skip_aware_bytes(256, sh3.P, fp3, ft3)
+        secondary["fwd_bwd_256_no_skip"] = {
+            "workload": "the 256^3 cloud with 50% of its 100k points replaced by uniform outliers "
+                        "(|n| ~ U[0, 0.05]): every plane and row tile holds points",
+            "solves_per_s": round(args.steps / d3, 2), "ms": round(ms3, 4),
+            "live_plane_fraction": round(fp3, 4), "live_tile_fraction": round(ft3, 4),
+            "algorithmic_bytes": round(sk3), "hbm_frac": round(rate(sk3, ms3) / HBM_PEAK_GBS, 4),
+            "dense_equivalent_frac": round(rate(b_stage(256, sh3.P), ms3) / HBM_PEAK_GBS, 4)}
+        del b3
+        sh1 = S.config_c1()
+        b1 = prepare(sh1, dev, torch, F)
+        f1 = make_step(b1, ctx, backward=False)
+        d1 = timed(f1, args.steps * 10, args.warmup, torch)
+        secondary["fwd_only_32"] = {"workload": "32^3, 3,000 points on a sphere, sigma 2, forward only",
+                                    "solves_per_s": round(args.steps * 10 / d1, 1),
+                                    "ms": round(d1 / (args.steps * 10) * 1e3, 4)}
+        del b1
         secondary["batch_c4"] = batch_c4(dev, torch)
+        if not args.no_serve:
+            secondary["serve_c5"] = serve_mode(dev, torch, args.serve_requests, levels=(1.0, 1.5))
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline()
+    gpu_result = None
+    if not args.no_cpu_baseline:
+        step()
+        torch.cuda.synchronize()
+        gpu_result = tuple(t.detach().cpu().numpy() for t in (b["chi"], b["dp"], b["dn"]))
+    cpu = None if args.no_cpu_baseline else cpu_baseline(gpu_result)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
@@ -532,7 +627,8 @@ def main():
         "config": {"workload": "fwd+bwd 256^3, 100k points on a superellipsoid (seed 2), noisy normals, sigma 2",
                    "res": r, "npoints": P, "sigma": shape.sigma, "precision": "FP32 grid, FP64 reductions",
                    "parallelism": "single GPU"},
-        "roofline": roof, "step_roofline": step_roof, "step_timing_50": timing, "stage_ms": breakdown,
+        "roofline": roof, "step_roofline_dense_equivalent": step_dense, "step_roofline_skip_aware": step_skip,
+        "step_timing_50": timing, "stage_ms": breakdown,
         "dominant_kernel_region_ms_per_step": round(dt2 / args.steps * 1e3, 4),
         "secondary": secondary, "cpu_baseline": cpu,
     }

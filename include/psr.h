@@ -105,23 +105,34 @@ int psr_forward(psr_ctx* ctx, const float* points, const float* normals, int64_t
                 int res, float sigma, float* chi, void* saved, void* workspace,
                 size_t workspace_bytes, hipStream_t stream);
 
-/* Backward (adjoint) of psr_forward: given dchi = dL/dchi, writes
- * dpoints = dL/dpoints and dnormals = dL/dnormals ([npoints][3] float32; either
- * may be NULL to skip it). `chi` is the forward's output and `saved` its state,
- * both unchanged since the forward; npoints/res/sigma must repeat the forward's.
- * The derivative of the position wrap (mod 1) is taken as 1; on a cell face the
- * derivative is the one of the cell above (right derivative). */
+/* Backward (adjoint) of psr_forward: the gradient of a loss L(chi) with
+ * respect to the oriented points that main Sec. 3.1 asks of the solver (the
+ * paper differentiates Eqs. 3-4 by autograd; here the adjoint is written out:
+ * transposed splat, conjugate spectral operator, transposed gather, and the
+ * derivative of the Eq. 4 normalisation through mean, c and m/|c|).
+ * Given dchi = dL/dchi, writes dpoints = dL/dpoints and dnormals = dL/dnormals
+ * ([npoints][3] float32; either may be NULL to skip it). `chi` is the
+ * forward's output and `saved` its state, both unchanged since the forward;
+ * npoints/res/sigma must repeat the forward's. The saved header records the
+ * forward's res and npoints: if they differ from this call's, every backward
+ * kernel returns without reading the saved records or the workspace, and
+ * dpoints/dnormals are filled with NaN (the call itself returns PSR_OK, as the
+ * check runs on the device). The derivative of the position wrap (mod 1) is
+ * taken as 1; on a cell face the derivative is the one of the cell above
+ * (right derivative). */
 int psr_backward(psr_ctx* ctx, int64_t npoints, int res, float sigma, const float* chi,
                  const void* saved, const float* dchi, float* dpoints, float* dnormals,
                  void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* Synchronises `stream`, then reads the status word written by the forward
- * on that stream into *status (PSR_OK, PSR_EDEGENERATE or PSR_ENONFINITE). */
+ * on that stream into *status (PSR_OK, PSR_EDEGENERATE or PSR_ENONFINITE).
+ * EDEGENERATE is the case where the scale of main Eq. 4 cannot be formed
+ * (c = 0 or non-finite, so m/|c| of Eq. 2's constraint is undefined). */
 int psr_saved_status(const void* saved, hipStream_t stream, int* status);
 
-/* Synchronises `stream`, then reads the forward's FP64 scalars: the mean of
- * chi' at the points, the scale denominator c, the scale m/|c| and chi'(0,0,0).
- * Any output pointer may be NULL. */
+/* Synchronises `stream`, then reads the forward's FP64 scalars of main Eq. 4:
+ * the mean of chi' at the points, the scale denominator c, the scale m/|c| and
+ * chi'(0,0,0). Any output pointer may be NULL. */
 int psr_saved_scalars(const void* saved, hipStream_t stream, double* mean, double* cscale,
                       double* scale, double* chi0);
 

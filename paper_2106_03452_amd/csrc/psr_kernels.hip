@@ -1884,6 +1884,17 @@ __device__ __forceinline__ int job_of(const Batch<MAXJ>& B, int blk) {
   (void)w;                                                            \
   (void)sv
 
+// Backward kernels: the saved state must come from a forward of the same
+// resolution and point count (its header records both). Otherwise the saved
+// records and the workspace would be indexed with the wrong layout, so every
+// backward kernel returns at once; the last one fills the gradients with NaN.
+template <int RES>
+__device__ __forceinline__ bool saved_mismatch(const SavedHeader* __restrict__ hdr, int64_t P) {
+  return hdr->res != RES || hdr->npoints != P;
+}
+#define PSR_BWD_GUARD(RES) \
+  if (saved_mismatch<RES>(sv.hdr, J.P)) return
+
 template <int RES, int MAXJ>
 __global__ __launch_bounds__(256) void k_init(const Batch<MAXJ> B) {
   PSR_JOB(RES);
@@ -1926,6 +1937,7 @@ __global__ __launch_bounds__(256) void k_scan_scatter(const Batch<MAXJ> B) {
 template <int RES, int MODE, int MAXJ>
 __global__ __launch_bounds__(rows_block(RES)) void k_splat_r2c(const Batch<MAXJ> B) {
   PSR_JOB(RES);
+  if constexpr (MODE == MODE_BWDH || MODE == MODE_BWDA) { PSR_BWD_GUARD(RES); }
   const float* gin = MODE == MODE_BWDH || MODE == MODE_BWDA ? J.dchi : J.aux_in;
   b_splat_r2c<RES, MODE>(sv.sorted, sv.off, gin, w.bs, (const double2*)w.blockpart, sv.hdr, B.tw, w.X, J.aux_out,
                          J.chi, (double2*)w.blockpart, bid);
@@ -1934,6 +1946,7 @@ __global__ __launch_bounds__(rows_block(RES)) void k_splat_r2c(const Batch<MAXJ>
 template <int RES, bool MERGE, bool SKIP, int MAXJ>
 __global__ __launch_bounds__(cols_block(RES)) void k_axis1_fwd(const Batch<MAXJ> B) {
   PSR_JOB(RES);
+  if constexpr (!MERGE) { PSR_BWD_GUARD(RES); }
   b_axis1_fwd<RES, MERGE, SKIP>(w.X, w.Y, B.tw, sv.hdr->tlive, bid);
 }
 
@@ -1947,18 +1960,21 @@ __global__ __launch_bounds__(j0_block(RES)) void k_fwd_axis0(const Batch<MAXJ> B
 template <int RES, int MAXJ>
 __global__ __launch_bounds__(j0_block(RES)) void k_bwd_axis0(const Batch<MAXJ> B) {
   PSR_JOB(RES);
+  PSR_BWD_GUARD(RES);
   b_bwd_axis0<RES, use_plane(RES)>(w.Y, w.X, B.tw, J.sigma, sv.off, bid);
 }
 
 template <int RES, bool SPLIT, int MAXJ>
 __global__ __launch_bounds__(cols_block(RES)) void k_axis1_inv(const Batch<MAXJ> B) {
   PSR_JOB(RES);
+  if constexpr (SPLIT) { PSR_BWD_GUARD(RES); }
   b_axis1_inv<RES, SPLIT>(w.X, w.Y, B.tw, sv.off, bid);
 }
 
 template <int RES, int MODE, int MAXJ>
 __global__ __launch_bounds__(rows_block(RES)) void k_c2r_gather(const Batch<MAXJ> B) {
   PSR_JOB(RES);
+  if constexpr (MODE == MODE_BWD) { PSR_BWD_GUARD(RES); }
   float* out = MODE == MODE_DBG ? J.aux_out : J.chi;
   b_c2r_gather<RES, MODE>(w.Y, out, sv.hdr, sv.sorted, sv.off, w.part, J.P, B.tw, bid);
 }
@@ -1967,6 +1983,7 @@ template <int RES, int MODE, int MAXJ>
 __global__ __launch_bounds__(Plane<RES>::BLOCK) __attribute__((amdgpu_waves_per_eu(Plane<RES>::WPE)))
 void k_plane_fwd(const Batch<MAXJ> B) {
   PSR_JOB(RES);
+  if constexpr (MODE == PF_BWDH) { PSR_BWD_GUARD(RES); }
   const float* gin = MODE == PF_BWDH ? J.dchi : J.aux_in;
   b_plane_fwd<RES, MODE>(sv.sorted, sv.off, gin, w.bs, (const double2*)w.blockpart, sv.hdr, B.tw, w.Y, bid);
 }
@@ -1975,6 +1992,7 @@ template <int RES, int MODE, int MAXJ>
 __global__ __launch_bounds__(Plane<RES>::BLOCK) __attribute__((amdgpu_waves_per_eu(Plane<RES>::WPE)))
 void k_plane_inv(const Batch<MAXJ> B) {
   PSR_JOB(RES);
+  if constexpr (MODE == PI_BWD) { PSR_BWD_GUARD(RES); }
   float* outp = MODE == PI_DBG ? J.aux_out : J.chi;
   b_plane_inv<RES, MODE>(w.X, outp, sv.hdr, sv.sorted, sv.off, w.part, J.P, B.tw, bid);
 }
@@ -2002,6 +2020,7 @@ __global__ __launch_bounds__(256) void k_normalize(const Batch<MAXJ> B) {
 template <int RES, int MAXJ>
 __global__ __launch_bounds__(256) void k_bwd_reduce(const Batch<MAXJ> B) {
   PSR_JOB(RES);
+  PSR_BWD_GUARD(RES);
   b_bwd_reduce(J.dchi, J.chi, (int64_t)RES * RES * RES, (double2*)w.blockpart, bid, nbl);
 }
 
@@ -2010,6 +2029,15 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(const Batch<MAXJ> B) {
 template <int RES, int MAXJ>
 __global__ __launch_bounds__(256) void k_bwd_point_finalize(const Batch<MAXJ> B) {
   PSR_JOB(RES);
+  if (saved_mismatch<RES>(sv.hdr, J.P)) {
+    const int64_t s = (int64_t)bid * blockDim.x + threadIdx.x;
+    const float nan = __int_as_float(0x7fc00000);
+    for (int k = 0; k < 3 && s < J.P; ++k) {
+      if (J.dpts) J.dpts[3 * s + k] = nan;
+      if (J.dnrm) J.dnrm[3 * s + k] = nan;
+    }
+    return;
+  }
   b_bwd_point_finalize(w.part, sv.gradf, sv.sorted, w.bs, J.P, J.dpts, J.dnrm, bid);
 }
 

@@ -48,7 +48,22 @@ def forward(points: torch.Tensor, normals: torch.Tensor, res: int, sigma: float 
                                 _ptr(chi), _ptr(saved), _ptr(workspace), ctypes.c_size_t(workspace.numel()),
                                 _stream(dev))
     _lib.check(rc, "psr_forward")
+    # the resolution and point count this state was made for; backward checks them
+    saved.psr_meta = (int(res), P)
     return chi, saved
+
+
+def _check_saved(chi: torch.Tensor, saved: torch.Tensor, npoints: int, res: int) -> None:
+    """Raise before any launch if (res, npoints) cannot be the forward's: the
+    kernels would index the saved state with the wrong layout."""
+    if tuple(chi.shape) != (res, res, res) or chi.dtype != torch.float32 or not chi.is_cuda:
+        raise ValueError(f"chi must be a CUDA float32 ({res},{res},{res}) tensor, got {tuple(chi.shape)} {chi.dtype}")
+    if saved.dtype != torch.uint8 or not saved.is_cuda or saved.numel() < _lib.saved_bytes(res, npoints):
+        raise ValueError(f"saved must be the uint8 state of a forward with res={res}, npoints={npoints}")
+    meta = getattr(saved, "psr_meta", None)
+    if meta is not None and meta != (int(res), int(npoints)):
+        raise ValueError(f"saved comes from a forward with (res, npoints) = {meta}, backward got "
+                         f"({res}, {npoints})")
 
 
 def backward(chi: torch.Tensor, saved: torch.Tensor, dchi: torch.Tensor, npoints: int, res: int,
@@ -56,6 +71,7 @@ def backward(chi: torch.Tensor, saved: torch.Tensor, dchi: torch.Tensor, npoints
              ctx: _lib.Context | None = None, workspace: torch.Tensor | None = None):
     """Run ``psr_backward``. Returns (dpoints or None, dnormals or None), each (P, 3)."""
     dev = chi.device
+    _check_saved(chi, saved, npoints, res)
     ctx = ctx or _lib.context(dev.index if dev.index is not None else torch.cuda.current_device())
     dchi = dchi.contiguous().to(torch.float32)
     if dchi.shape != chi.shape:

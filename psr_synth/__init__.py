@@ -23,7 +23,8 @@ import numpy as np
 
 __all__ = [
     "rng_for", "sphere", "torus", "superellipsoid", "random_rotation",
-    "Shape", "config_c1", "config_c2", "config_c2_outliers", "config_c3", "config_c4", "config_c5",
+    "Shape", "config_c1", "config_c2", "config_c2_outliers", "config_c3", "config_c3_outliers", "config_c4",
+    "config_c5",
     "random_shape", "tiny_case", "loss_gradient", "thin_plate",
 ]
 
@@ -214,6 +215,23 @@ def config_c3(seed: int = 2, P: int = 100000, table=(2048, 4096)) -> Shape:
                  meta=dict(axes=axes.tolist(), eps1=float(e1), eps2=float(e2)))
 
 
+def config_c3_outliers(seed: int = 2, P: int = 100000, frac: float = 0.5) -> Shape:
+    """The C3 cloud (256^3) with a fraction of its points replaced by outliers:
+    uniform in [0,1)^3, random directions, |n| ~ U[0, 0.05]. With half of 100k
+    points uniform, every j0 plane and every row tile holds points, so no pass
+    can skip anything (the dense worst case of the byte model)."""
+    base = config_c3(seed, P)
+    rng = rng_for(seed + 1000)
+    k = int(round(frac * P))
+    idx = rng.choice(P, k, replace=False)
+    p = base.points.astype(np.float64)
+    n = base.normals.astype(np.float64)
+    p[idx] = rng.uniform(0.0, 1.0, (k, 3))
+    n[idx] = _unit(rng.standard_normal((k, 3))) * rng.uniform(0.0, 0.05, (k, 1))
+    return Shape(256, 2.0, _f32(p), _f32(n), base.points_clean, base.normals_clean,
+                 kind="superellipsoid+outliers", meta=dict(outliers=k))
+
+
 def random_shape(rng, res: int, P: int, sigma: float = 2.0, table=(256, 512)) -> Shape:
     """One shape of the mixed batch/serving workloads: sphere, rotated torus or superellipsoid."""
     kind = ["sphere", "torus", "superellipsoid"][int(rng.integers(0, 3))]
@@ -242,22 +260,35 @@ def config_c4(seed: int = 3, n_shapes: int = 64) -> list[Shape]:
     return out
 
 
-def config_c5(seed: int = 4, n_requests: int = 2000):
+def _c5_shape(args):
+    res, P, seed = args
+    return random_shape(rng_for(seed), res, P)
+
+
+def config_c5(seed: int = 4, n_requests: int = 2000, workers: int = 1):
     """Serving request stream: res in {64,128,256}, P log-uniform [3e3, 2e5], 50/50 fwd vs fwd+bwd.
 
     Returns a list of (Shape, needs_backward) in arrival order; inter-arrival
     times are drawn separately by the load generator for each QPS level as
-    unit-rate exponentials (``arrivals_unit``), scaled by 1/QPS.
+    unit-rate exponentials (``arrivals_unit``), scaled by 1/QPS. Each request's
+    shape comes from its own seed (drawn from the stream's generator), so a
+    process pool of ``workers`` can build them in parallel with the same result.
     """
     rng = rng_for(seed)
-    reqs = []
+    specs, bwds = [], []
     for _ in range(n_requests):
         res = int(rng.choice([64, 128, 256]))
         P = int(round(math.exp(rng.uniform(math.log(3e3), math.log(2e5)))))
-        bwd = bool(rng.uniform() < 0.5)
-        reqs.append((random_shape(rng, res, P), bwd))
+        bwds.append(bool(rng.uniform() < 0.5))
+        specs.append((res, P, int(rng.integers(0, 2 ** 62))))
     arrivals_unit = rng.exponential(1.0, n_requests)
-    return reqs, arrivals_unit
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            shapes = pool.map(_c5_shape, specs, chunksize=8)
+    else:
+        shapes = [_c5_shape(a) for a in specs]
+    return list(zip(shapes, bwds)), arrivals_unit
 
 
 def thin_plate(seed: int, P: int, res: int, half_thickness: float = 0.006, table=(256, 512)) -> Shape:

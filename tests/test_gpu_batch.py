@@ -16,13 +16,13 @@ def dev():
     return require_gpu()
 
 
-def _mixed_jobs(dev, n, seed, with_bwd=True, res_choices=(16, 32, 64)):
+def _mixed_jobs(dev, n, seed, with_bwd=True, res_choices=(16, 32, 64), pmax=4000):
     from paper_2106_03452_amd.batch import Job
     rng = np.random.Generator(np.random.PCG64(seed))
     jobs, shapes = [], []
     for i in range(n):
         res = int(rng.choice(res_choices))
-        P = int(round(np.exp(rng.uniform(np.log(50), np.log(4000)))))
+        P = int(round(np.exp(rng.uniform(np.log(50), np.log(pmax)))))
         sh = S.random_shape(rng, res, P)
         G = rng.standard_normal((res, res, res)).astype(np.float32) if (with_bwd and i % 3 != 1) else None
         jobs.append(Job(to_dev(sh.points, dev), to_dev(sh.normals, dev), res, 2.0,
@@ -52,10 +52,11 @@ def test_batch_equals_solo(dev, n, res_choices):
             assert dp_b is None and dn_b is None
 
 
-def test_batch_against_oracle(dev):
-    announce("batch vs oracle")
+@pytest.mark.parametrize("n,res_choices,pmax", [(6, (16, 32, 64), 4000), (6, (64, 128), 50000)])
+def test_batch_against_oracle(dev, n, res_choices, pmax):
+    announce(f"batch of {n} jobs res {res_choices} vs oracle")
     from paper_2106_03452_amd.batch import BatchPlan
-    jobs, shapes = _mixed_jobs(dev, 6, 1)
+    jobs, shapes = _mixed_jobs(dev, n, 1, res_choices=res_choices, pmax=pmax)
     plan = BatchPlan(jobs)
     plan.run()
     torch.cuda.synchronize()

@@ -293,3 +293,38 @@ def test_splat_is_bitwise_deterministic(psr, dev, res, P, kind):
     pts, nrm = to_dev(sh.points, dev), to_dev(sh.normals, dev)
     assert torch.equal(psr.debug_splat(pts, nrm, res), psr.debug_splat(pts, nrm, res))
 
+
+
+def test_backward_refuses_state_of_another_solve(psr, dev):
+    """psr_backward must repeat the forward's res and npoints. The binding
+    raises before any launch; called through the C ABI with smaller values
+    (so every buffer stays in bounds either way), the kernels see the saved
+    header's res/npoints differ and the gradients come back NaN."""
+    import ctypes
+    from paper_2106_03452_amd import _lib
+    announce("backward with mismatched res / npoints")
+    sh = S.tiny_case(21, 32, 3000, kind="sphere")
+    pts, nrm = to_dev(sh.points, dev), to_dev(sh.normals, dev)
+    chi, saved = psr.forward(pts, nrm, 32, 2.0)
+    G = torch.ones_like(chi)
+    with pytest.raises(ValueError):
+        psr.backward(chi, saved, G, 2900, 32, 2.0)
+    with pytest.raises(ValueError):
+        psr.backward(chi, saved, G, 3000, 16, 2.0)
+    L = _lib.lib()
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    for res, P in ((32, 2900), (16, 3000)):
+        ws = torch.empty(_lib.workspace_bytes(res, P), dtype=torch.uint8, device=dev)
+        g = torch.ones((res, res, res), dtype=torch.float32, device=dev)
+        c = chi if res == 32 else torch.zeros((16, 16, 16), dtype=torch.float32, device=dev)
+        dp = torch.zeros((P, 3), dtype=torch.float32, device=dev)
+        dn = torch.zeros((P, 3), dtype=torch.float32, device=dev)
+        rc = L.psr_backward(_lib.context(0).handle, P, res, 2.0, p(c), p(saved), p(g), p(dp), p(dn), p(ws),
+                            ctypes.c_size_t(ws.numel()), st)
+        assert rc == 0
+        torch.cuda.synchronize()
+        assert torch.isnan(dp).all() and torch.isnan(dn).all(), (res, P)
+    # the matching call still works
+    dp, dn = psr.backward(chi, saved, G, 3000, 32, 2.0)
+    assert torch.isfinite(dp).all() and torch.isfinite(dn).all()

@@ -15,15 +15,20 @@ def dev():
     return require_gpu()
 
 
-def test_results_same_alone_and_in_the_mix(dev):
-    announce("serve: 48 requests, 3 streams, vs solo")
+@pytest.mark.parametrize("n,res_choices,pmax,streams", [(48, (16, 32, 64), 6000, 3),
+                                                         (16, (64, 128, 256), 200000, 4)])
+def test_results_same_alone_and_in_the_mix(dev, n, res_choices, pmax, streams):
+    """Small grids with many requests per batch, and the serving stream's own
+    grid sizes and point counts (64/128/256, up to 200k points: the plane and
+    row passes of every size overlap on several streams)."""
+    announce(f"serve: {n} requests res {res_choices}, {streams} streams, vs solo")
     from paper_2106_03452_amd import function as F
     from paper_2106_03452_amd.serve import Engine, GpuBackend, Request, drive
     rng = np.random.Generator(np.random.PCG64(5))
     reqs, inputs = [], []
-    for i in range(48):
-        res = int(rng.choice([16, 32, 64]))
-        P = int(round(np.exp(rng.uniform(np.log(100), np.log(6000)))))
+    for i in range(n):
+        res = int(rng.choice(res_choices))
+        P = int(round(np.exp(rng.uniform(np.log(100), np.log(pmax)))))
         sh = S.random_shape(rng, res, P)
         bwd = bool(rng.uniform() < 0.5)
         pts, nrm = to_dev(sh.points, dev), to_dev(sh.normals, dev)
@@ -33,11 +38,12 @@ def test_results_same_alone_and_in_the_mix(dev):
                     out_dpoints=torch.empty((P, 3), device=dev) if bwd else None,
                     out_dnormals=torch.empty((P, 3), device=dev) if bwd else None)
         reqs.append(r)
-    be = GpuBackend(0, num_streams=3)
-    eng = Engine(be, {16: 6000, 32: 6000, 64: 6000}, hbm_budget=2 << 30, max_batch=8)
+    be = GpuBackend(0, num_streams=streams)
+    eng = Engine(be, {r: pmax for r in res_choices}, hbm_budget=(2 << 30) if pmax <= 6000 else (24 << 30),
+                 max_batch=8)
     drive(eng, reqs)
     torch.cuda.synchronize()
-    assert len(eng.finished) == 48 and not eng.rejected
+    assert len(eng.finished) == n and not eng.rejected
     assert all(r.error is None and r.latency >= 0 for r in eng.finished)
     for r in reqs:
         chi, saved = F.forward(r.points, r.normals, r.res, 2.0)
