@@ -29,10 +29,14 @@
  * the backward reductions sum G and sum G*chi are accumulated in FP64.
  *
  * Memory: every pointer argument is DEVICE memory owned by the caller unless
- * stated otherwise. The library allocates nothing per call: grid-sized scratch
- * comes in through `workspace` (size from psr_workspace_bytes) and the
- * per-solve state that backward needs lives in `saved` (size from
- * psr_saved_bytes). Buffers must be 256-byte aligned.
+ * stated otherwise. Grid-sized scratch comes in through `workspace` (size from
+ * psr_workspace_bytes) and the per-solve state that backward needs lives in
+ * `saved` (size from psr_saved_bytes), both owned by the caller, so a solve's
+ * state lives exactly as long as the caller keeps its buffers and no free
+ * call is needed. The library allocates only per context: its twiddle tables
+ * at psr_ctx_create and one point-source table per (res, sigma) at the first
+ * backward of that size (or at psr_ctx_prepare). Buffers must be 256-byte
+ * aligned.
  *
  * Asynchrony: psr_forward, psr_backward and psr_run_batched only enqueue
  * kernels on `stream` and return. Argument errors are reported at once and
@@ -123,6 +127,20 @@ int psr_forward(psr_ctx* ctx, const float* points, const float* normals, int64_t
 int psr_backward(psr_ctx* ctx, int64_t npoints, int res, float sigma, const float* chi,
                  const void* saved, const float* dchi, float* dpoints, float* dnormals,
                  void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Build the backward's point-source table for (res, sigma) now, on `stream`
+ * (synchronising it once), instead of on the first psr_backward or
+ * psr_run_batched call with that size. The table is the response of the
+ * adjoint spectral operator of main Eq. 3 to a unit source at grid vertex 0:
+ * the derivative of Eq. 4 through chi'(0,0,0) puts a point source of weight
+ * -Q = -sum(G chi)/c at that vertex, whose FP32 transform alongside the rest
+ * of the cotangent would lose its precision when Q is large, so its effect
+ * is read at the points from this table, built in FP64 and kept as float
+ * ((res/2 + 1)^3 floats, 8.6 MB at 256^3) until psr_ctx_destroy. The first
+ * backward at a new (res, sigma) allocates the table and a temporary build
+ * buffer and synchronises its stream; later calls allocate nothing.
+ * Returns PSR_EINVAL, PSR_ENOMEM or PSR_EDEVICE on failure. */
+int psr_ctx_prepare(psr_ctx* ctx, int res, float sigma, hipStream_t stream);
 
 /* Synchronises `stream`, then reads the status word written by the forward
  * on that stream into *status (PSR_OK, PSR_EDEGENERATE or PSR_ENONFINITE).

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -84,6 +85,15 @@ struct psr_ctx {
   double m = 0.5;
   int reading = 0;
   psr::Timers* timers = nullptr;
+  // point-source tables of the backward, one per (res, sigma), kept until
+  // the context is destroyed
+  struct KTab {
+    int res;
+    float sigma;
+    float* table;
+  };
+  std::mutex kmu;
+  std::vector<KTab> ktabs;
 };
 
 namespace {
@@ -120,6 +130,7 @@ psr::JobArg make_job(const float* pts, const float* nrm, int64_t P, float sigma,
   j.sv = saved;
   j.aux_in = nullptr;
   j.aux_out = nullptr;
+  j.ktab = nullptr;
   j.P = P;
   j.sigma = sigma;
   j.pad = 0;
@@ -134,6 +145,37 @@ psr::Exec make_exec(psr_ctx* ctx, hipStream_t stream) {
   x.reading = ctx->reading;
   x.timers = ctx->timers;
   return x;
+}
+
+// The backward's point-source table of (res, sigma): built on first use,
+// in FP64 on `stream` (a one-time allocation of the table and of its build
+// scratch, then a synchronisation of `stream` so that every stream may read
+// it), then reused.
+int point_source_table(psr_ctx* ctx, int res, float sigma, hipStream_t stream, const float** out) {
+  std::lock_guard<std::mutex> lk(ctx->kmu);
+  for (const auto& k : ctx->ktabs) {
+    if (k.res == res && k.sigma == sigma) {
+      *out = k.table;
+      return PSR_OK;
+    }
+  }
+  float* table = nullptr;
+  void* scratch = nullptr;
+  if (hipMalloc(&table, psr::ktab_floats(res) * sizeof(float)) != hipSuccess) return PSR_ENOMEM;
+  if (hipMalloc(&scratch, psr::ktab_scratch_bytes(res)) != hipSuccess) {
+    (void)hipFree(table);
+    return PSR_ENOMEM;
+  }
+  int rc = psr::build_point_source_table(res, sigma, table, scratch, stream) ? PSR_EDEVICE : PSR_OK;
+  if (hipStreamSynchronize(stream) != hipSuccess) rc = PSR_EDEVICE;
+  (void)hipFree(scratch);
+  if (rc) {
+    (void)hipFree(table);
+    return rc;
+  }
+  ctx->ktabs.push_back({res, sigma, table});
+  *out = table;
+  return PSR_OK;
 }
 
 const char* const kStageNames[psr::NUM_STAGES] = {
@@ -198,6 +240,7 @@ int psr_ctx_destroy(psr_ctx* ctx) {
   DeviceGuard g(ctx->device);
   delete ctx->timers;
   if (ctx->tw) (void)hipFree(ctx->tw);
+  for (auto& k : ctx->ktabs) (void)hipFree(k.table);
   delete ctx;
   return PSR_OK;
 }
@@ -280,13 +323,23 @@ int psr_backward(psr_ctx* ctx, int64_t npoints, int res, float sigma, const floa
     return PSR_EINVAL;
   if (workspace_bytes < psr::ws_layout(res, npoints).total) return PSR_EINVAL;
   DeviceGuard g(ctx->device);
+  const float* kt = nullptr;
+  if (int rc = point_source_table(ctx, res, sigma, stream, &kt)) return rc;
   psr::Exec x = make_exec(ctx, stream);
   psr::JobArg j = make_job(nullptr, nullptr, npoints, sigma, const_cast<float*>(chi), const_cast<void*>(saved),
                            workspace);
+  j.ktab = kt;
   j.dchi = dchi;
   j.dpts = dpoints;
   j.dnrm = dnormals;
   return psr::run_jobs(x, res, &j, 1, psr::RUN_BACKWARD);
+}
+
+int psr_ctx_prepare(psr_ctx* ctx, int res, float sigma, hipStream_t stream) {
+  if (!ctx || !valid_res(res) || !(sigma >= 0.0f) || !std::isfinite(sigma)) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  const float* kt = nullptr;
+  return point_source_table(ctx, res, sigma, stream, &kt);
 }
 
 int psr_saved_status(const void* saved, hipStream_t stream, int* status) {
@@ -339,6 +392,7 @@ int psr_run_batched(psr_ctx* ctx, int njobs, const psr_job* jobs, hipStream_t st
         a.dchi = j.dchi;
         a.dpts = j.dpoints;
         a.dnrm = j.dnormals;
+        if (int rc = point_source_table(ctx, res, j.sigma, stream, &a.ktab)) return rc;
         bw.push_back(a);
       }
     }

@@ -180,6 +180,7 @@ struct JobArg {
   void* sv;
   const float* aux_in;  // test hooks: field v in
   float* aux_out;       // test hooks: field v out
+  const float* ktab;    // backward: point-source table of (res, sigma)
   int64_t P;
   float sigma;
   int pad;
@@ -219,6 +220,21 @@ struct Exec {
 };
 
 enum RunWhat { RUN_FORWARD = 1, RUN_BACKWARD = 2 };
+
+// Point-source table of the backward (see build_point_source_table): floats
+// on the octant [0, res/2]^3, and the FP64 scratch its build needs.
+__host__ __device__ inline size_t ktab_floats(int res) {
+  const size_t h = (size_t)res / 2 + 1;
+  return h * h * h;
+}
+__host__ __device__ inline size_t ktab_scratch_bytes(int res) {
+  const size_t h = (size_t)res / 2 + 1;
+  return 2 * align256(h * h * h * 8) + 2 * align256(h * h * 8);
+}
+// Build the table of (res, sigma) into `table` (ktab_floats(res) floats) with
+// `scratch` (ktab_scratch_bytes(res) bytes) as FP64 temporaries; enqueued on
+// `stream`. Returns 0 or -4 (launch failure).
+int build_point_source_table(int res, float sigma, float* table, void* scratch, hipStream_t stream);
 
 // Run forward and/or backward for n jobs of one resolution.
 int run_jobs(Exec& x, int res, const JobArg* jobs, int n, int what);

@@ -19,10 +19,14 @@
 // cotangent H, conjugate operator, 3 inverse channels, gather of dL/dv), with
 // the same pass structure (B1..B5, B12, B45); on the two-pass path the sums
 // ride on a first cotangent pass (B1a) that also transforms the row tiles
-// needing no backward scalar. Planes and row tiles that no point reaches are
+// needing no backward scalar. The cotangent's point source -Q delta_0 (the
+// derivative through chi'(0,0,0) in Eq. 4) is not transformed: its response
+// is read at the points from a table built once per (res, sigma) in FP64
+// (a spike of that size would set the FP32 rounding of every spectrum
+// element). Planes and row tiles that no point reaches are
 // skipped where their values are zero or unused (bitmaps from the bin
-// offsets). The splat accumulates fixed-point integers in LDS (bitwise
-// reproducible) unless a span is very dense.
+// offsets). The splat accumulates 64-bit fixed-point integers in LDS
+// (bitwise reproducible at any density).
 //
 // Layouts (complex64 unless noted; H = r/2 + 1 half-spectrum planes):
 //   A[c][k2][j0][j1]   P1 out, P2 in   (3 channels fwd, 1 bwd)
@@ -478,11 +482,11 @@ __device__ __forceinline__ void scan_to_lds(const int* __restrict__ counts, int*
 // ---------------------------------------------------------------------------
 // P1 / B1: rasterise one channel into LDS rows, then r2c FFT along j2.
 // MODE_SPLAT: v_c = splat of normal component c        [forward, grid x3]
-// MODE_BWDH : H = s G + alpha W - Q delta_0 (1 channel)   [backward]
+// MODE_BWDH : H = s G + alpha W (1 channel)              [backward]
 // MODE_LOADV: v_c loaded from global                     [spectral test hook]
 // MODE_VOUT : splat only, rows written to global v_c      [splat test hook]
 // MODE_BWDA : the FP64 partials of S_G and S_Gchi per row tile, and H = s G
-//             for the row tiles that W and delta_0 do not reach  [backward,
+//             for the row tiles that W does not reach    [backward,
 //             before MODE_BWDH, which then takes only the other tiles]
 // ---------------------------------------------------------------------------
 enum { MODE_SPLAT = 0, MODE_BWDH = 1, MODE_LOADV = 2, MODE_VOUT = 3, MODE_BWDA = 4 };
@@ -544,9 +548,11 @@ __device__ __forceinline__ float3 bwd_scalars(const double2* __restrict__ blockp
 
 // Rows [a0, a0 + NROWS) of plane j0 of one channel into LDS as float samples
 // (row l, sample n at float slot 2 rpos(l, n/2) + (n & 1)). KIND 0: splat of
-// normal component ch over the points of R; KIND 1: the cotangent
-// H = s G - Q delta_0 + alpha W (W = splat of ones, G from gin); KIND 2: rows
-// of v_ch from gin. Ends with a barrier.
+// normal component ch over the points of R; KIND 1: the cotangent without
+// its point source at vertex 0, H = s G + alpha W (W = splat of ones, G from
+// gin; the -Q delta_0 term is applied at the points from the point-source
+// table, see b_bwd_point_finalize); KIND 2: rows of v_ch from gin. Ends with a
+// barrier.
 template <int RES, int NROWS, int BLOCK, int KIND>
 __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__ sorted, const Ranges& R,
                                           const float* __restrict__ gin, float3 sqa, int j0, int a0, int ch) {
@@ -557,8 +563,8 @@ __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__
   constexpr int NV = NROWS * M / 2;  // float4 = two complex slots
   constexpr int IT = (NV + BLOCK - 1) / BLOCK;
   if (KIND == 2 || (KIND == 1 && R.total == 0)) {
-    // rows straight from memory: v_ch (KIND 2), or s G - Q delta_0 where no
-    // point adds to W (KIND 1; uniform over the workgroup)
+    // rows straight from memory: v_ch (KIND 2), or s G where no point adds
+    // to W (KIND 1; uniform over the workgroup)
     const float sg = KIND == 1 ? sqa.x : 1.0f;
     const float4* g4 = reinterpret_cast<const float4*>(gin + (KIND == 2 ? ch * N3 : 0) + ((int64_t)j0 * RES + a0) * RES);
     float4 buf[IT];
@@ -572,16 +578,14 @@ __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__
       const int e = t + it * BLOCK;
       if (e < NV) {
         const int mm = (2 * e) % M, l = (2 * e) / M;
-        cf z0{buf[it].x * sg, buf[it].y * sg};
-        if (KIND == 1 && j0 == 0 && a0 + l == 0 && mm == 0) z0.x -= sqa.y;
-        rows[rpos<M>(l, mm)] = z0;
+        rows[rpos<M>(l, mm)] = cf{buf[it].x * sg, buf[it].y * sg};
         rows[rpos<M>(l, mm + 1)] = cf{buf[it].z * sg, buf[it].w * sg};
       }
     }
   } else if constexpr (KIND != 2) {
     // splat of normal component ch (or of unit weights: W in the backward)
     // in 64-bit fixed point, then back to floats, and in the backward
-    // H = s G - Q delta_0 + alpha W. A complex LDS slot (8 bytes) holds two
+    // H = s G + alpha W. A complex LDS slot (8 bytes) holds two
     // samples as floats but one as a 64-bit integer, so the samples are
     // accumulated in two rounds in place: even samples (the real parts),
     // then odd samples; the even sums wait in registers meanwhile.
@@ -661,10 +665,9 @@ __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__
           const int i0 = rpos<M>(l, mm), i1 = rpos<M>(l, mm + 1);
           float x0 = (float)(long long)r64[i0] * inv, x1 = (float)(long long)r64[i1] * inv;
           if constexpr (KIND == 1) {
-            // H = s G + alpha W - Q delta_0
+            // H = s G + alpha W
             x0 = alpha * x0 + sqa.x * (par ? gbuf[it].y : gbuf[it].x);
             x1 = alpha * x1 + sqa.x * (par ? gbuf[it].w : gbuf[it].z);
-            if (par == 0 && j0 == 0 && a0 + l == 0 && mm == 0) x0 -= sqa.y;
           }
           if (par == 0) {
             even[it] = make_float2(x0, x1);
@@ -784,18 +787,18 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
     if (total == 0) return;
   }
 
-  // the row tile holding vertex 0 (workgroup 0) carries the -Q delta_0 term
-  const bool has_delta = j0 == 0 && a0 == 0;
+  // the row tile of workgroup 0 records the backward scalars for the final pass
+  const bool records = T == 0;
   if constexpr (MODE == MODE_BWDA) {
-    // rows of tiles that W and delta_0 reach wait for the reductions (MODE_BWDH)
-    const bool later = total > 0 || has_delta;
+    // rows of tiles that W reaches wait for the reductions (MODE_BWDH)
+    const bool later = total > 0 || records;
     bwda_rows<RES, TR, BR>(rows, gin, chi_in, (float)hdr->scale, j0, a0, bpart_w + T, !later);
     if (later) return;
   } else {
     float3 sqa = make_float3(1.0f, 0.0f, 1.0f);
     if constexpr (MODE == MODE_BWDH) {
-      if (total == 0 && !has_delta) return;  // done by MODE_BWDA
-      sqa = bwd_scalars<BR>(bpart, RES * NT, hdr, bs, T == 0);
+      if (total == 0 && !records) return;  // done by MODE_BWDA
+      sqa = bwd_scalars<BR>(bpart, RES * NT, hdr, bs, records);
     }
     fill_rows<RES, TR, BR, MODE == MODE_VOUT ? MODE_SPLAT : MODE>(rows, sorted, R, gin, sqa, j0, a0, c);
   }
@@ -1380,7 +1383,7 @@ enum { PF_SPLAT = 0, PF_BWDH = 1, PF_LOADV = 2 };
 // Rows [a0, a0 + RC) of plane j0 of one channel into LDS (real samples at
 // float slot 2 rpos(l, n/2) + (n & 1)), then the half-length FFT of each row in
 // place. PF_SPLAT: trilinear splat of normal component ch; PF_BWDH: the
-// cotangent H = s G + alpha W - Q delta_0; PF_LOADV: v_ch rows from memory.
+// cotangent H = s G + alpha W; PF_LOADV: v_ch rows from memory.
 // Returns false, uniformly and before any barrier, when a splat span holds
 // no point (its rows and spectra are zero and LDS is left untouched).
 template <int RES, int MODE>
@@ -1811,11 +1814,33 @@ __device__ __forceinline__ void b_bwd_reduce(const float* __restrict__ G, const 
   if (threadIdx.x == 0) blockpart[bid] = make_double2(a, b);
 }
 
-// Q = S_Gchi / c, g_mu = -s S_G + Q (reading B; reading A drops Q), alpha = g_mu / P.
+// The response of the backward to the point source -Q delta_0 at a grid
+// vertex v, channel d: K_d(v) = Re IFFT(conj(A_d))(v), A_d the operator of
+// main Eq. 3 for channel d. K_0 is odd in j0 and even in j1 and j2, and K_d
+// is K_0 with axes d and 0 exchanged, so one octant [0, r/2]^3 of K_0
+// (ktab[(i0 (h) + i1) h + i2], h = r/2 + 1) serves all three channels.
+template <int RES>
+__device__ __forceinline__ float ktab_at(const float* __restrict__ kt, int d, int v0, int v1, int v2) {
+  constexpr int H = RES / 2, HP = H + 1;
+  const int a = d == 0 ? v0 : (d == 1 ? v1 : v2);
+  const int b = d == 0 ? v1 : v0;
+  const int c = d == 2 ? v1 : v2;
+  const bool neg = a > H;
+  const int ia = neg ? RES - a : a, ib = b > H ? RES - b : b, ic = c > H ? RES - c : c;
+  const float k = kt[((int64_t)ia * HP + ib) * HP + ic];
+  return neg ? -k : k;
+}
 
+// dn = sum of the 4 corner-line partials of each channel (gather of dL/dv),
+// dc = sum over channels of n_d times the weight-gradient partials, plus
+// alpha grad chi'(c_i) (the mean term); then the point source -Q delta_0 of
+// the cotangent, applied here from the table: -Q K_d gathered at the point
+// into dn_d, and -Q sum_d n_d K_d through the weight gradient into dc.
+template <int RES>
 __device__ __forceinline__ void b_bwd_point_finalize(const float4* __restrict__ part, const float4* __restrict__ gradf,
                                      const PointRec* __restrict__ sorted, const BwdScalars* __restrict__ bs,
-                                     int64_t npoints, float* __restrict__ dpoints, float* __restrict__ dnormals, int bid) {
+                                     const float* __restrict__ ktab, int64_t npoints, float* __restrict__ dpoints,
+                                     float* __restrict__ dnormals, int bid) {
   const int64_t s = (int64_t)bid * blockDim.x + threadIdx.x;
   if (s >= npoints) return;
   float4 p0, p1;
@@ -1842,6 +1867,34 @@ __device__ __forceinline__ void b_bwd_point_finalize(const float4* __restrict__ 
   dc[0] += alpha * g.x;
   dc[1] += alpha * g.y;
   dc[2] += alpha * g.z;
+  {
+    const float mq = -bs->q;
+    const uint32_t bb = __float_as_uint(p0.w);
+    const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
+    const float f[3] = {p0.x, p0.y, p0.z};
+    float kn[3] = {0.0f, 0.0f, 0.0f}, kc[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const int o0 = o & 1, o1 = (o >> 1) & 1, o2 = o >> 2;
+      const int v0 = (b0 + o0) & (RES - 1), v1 = (b1 + o1) & (RES - 1), v2 = (b2 + o2) & (RES - 1);
+      const float w0 = o0 ? f[0] : 1.0f - f[0], w1 = o1 ? f[1] : 1.0f - f[1], w2 = o2 ? f[2] : 1.0f - f[2];
+      const float k0 = ktab_at<RES>(ktab, 0, v0, v1, v2), k1 = ktab_at<RES>(ktab, 1, v0, v1, v2),
+                  k2 = ktab_at<RES>(ktab, 2, v0, v1, v2);
+      const float w = (w0 * w1) * w2;
+      kn[0] += w * k0;
+      kn[1] += w * k1;
+      kn[2] += w * k2;
+      const float nk = nv[0] * k0 + nv[1] * k1 + nv[2] * k2;
+      kc[0] += (o0 ? 1.0f : -1.0f) * (w1 * w2) * nk;
+      kc[1] += (o1 ? 1.0f : -1.0f) * (w0 * w2) * nk;
+      kc[2] += (o2 ? 1.0f : -1.0f) * (w0 * w1) * nk;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      dn[d] += mq * kn[d];
+      dc[d] += mq * ((float)RES * kc[d]);
+    }
+  }
   const int64_t i = (int64_t)__float_as_uint(p1.w);
   if (dpoints) {
     dpoints[3 * i + 0] = dc[0];
@@ -1853,6 +1906,92 @@ __device__ __forceinline__ void b_bwd_point_finalize(const float4* __restrict__ 
     dnormals[3 * i + 1] = dn[1];
     dnormals[3 * i + 2] = dn[2];
   }
+}
+
+// ---------------------------------------------------------------------------
+// Point-source table, built in FP64 once per (res, sigma). With h = r/2 and
+// the spectrum folded onto k in [0, h]^3 (K_0 is a sine series along k0 and
+// cosine series along k1, k2; wk = 1 at k = 0 and h, 2 between):
+//   K_0(j) = -(2/N) sum_{k0=1}^{h-1} sum_{k1,k2=0}^{h} wk1 wk2 g(k) k0 /
+//            (2 pi |k|^2) sin(2 pi k0 j0 / r) cos(2 pi k1 j1 / r) cos(2 pi k2 j2 / r)
+// (g the Gaussian of main Eq. 3; the Nyquist k0 = h carries no odd factor).
+// Three separable passes over the octant, each one output per thread.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ktab_trig(double* __restrict__ cs, double* __restrict__ sn, int r) {
+  const int hp = r / 2 + 1;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= hp * hp) return;
+  const int k = e / hp, j = e % hp;
+  double sv, cv;
+  sincospi(2.0 * (double)((k * j) % r) / (double)r, &sv, &cv);
+  cs[e] = cv;
+  sn[e] = sv;
+}
+
+__device__ __forceinline__ double ktab_g1(int k, double sigma, int r) {
+  return exp(-2.0 * sigma * sigma * (double)k * (double)k / ((double)r * (double)r));
+}
+
+// pass 1: A1[k0][k1][j2] = sum_k2 wk2 g1(k2) cos(k2 j2) / (k0^2 + k1^2 + k2^2)   (k0 >= 1)
+__global__ __launch_bounds__(256) void k_ktab_pass1(const double* __restrict__ cs, double* __restrict__ out,
+                                                    double sigma, int r) {
+  const int h = r / 2, hp = h + 1;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)hp * hp * hp) return;
+  const int j2 = (int)(e % hp), k1 = (int)((e / hp) % hp), k0 = (int)(e / ((int64_t)hp * hp));
+  double acc = 0.0;
+  if (k0 >= 1 && k0 < h) {
+    const double q = (double)k0 * k0 + (double)k1 * k1;
+    for (int k2 = 0; k2 <= h; ++k2) {
+      const double wk = (k2 == 0 || k2 == h) ? 1.0 : 2.0;
+      acc += wk * ktab_g1(k2, sigma, r) * cs[k2 * hp + j2] / (q + (double)k2 * k2);
+    }
+  }
+  out[e] = acc;
+}
+
+// pass 2: A2[k0][j1][j2] = sum_k1 wk1 g1(k1) cos(k1 j1) A1[k0][k1][j2]
+__global__ __launch_bounds__(256) void k_ktab_pass2(const double* __restrict__ cs, const double* __restrict__ in,
+                                                    double* __restrict__ out, double sigma, int r) {
+  const int h = r / 2, hp = h + 1;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)hp * hp * hp) return;
+  const int j2 = (int)(e % hp), j1 = (int)((e / hp) % hp), k0 = (int)(e / ((int64_t)hp * hp));
+  double acc = 0.0;
+  for (int k1 = 0; k1 <= h; ++k1) {
+    const double wk = (k1 == 0 || k1 == h) ? 1.0 : 2.0;
+    acc += wk * ktab_g1(k1, sigma, r) * cs[k1 * hp + j1] * in[((int64_t)k0 * hp + k1) * hp + j2];
+  }
+  out[e] = acc;
+}
+
+// pass 3: K_0[j0][j1][j2] = -(2/N) / (2 pi) sum_{k0=1}^{h-1} k0 g1(k0) sin(k0 j0) A2[k0][j1][j2]
+__global__ __launch_bounds__(256) void k_ktab_pass3(const double* __restrict__ sn, const double* __restrict__ in,
+                                                    float* __restrict__ table, double sigma, int r) {
+  const int h = r / 2, hp = h + 1;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)hp * hp * hp) return;
+  const int j2 = (int)(e % hp), j1 = (int)((e / hp) % hp), j0 = (int)(e / ((int64_t)hp * hp));
+  double acc = 0.0;
+  for (int k0 = 1; k0 < h; ++k0)
+    acc += (double)k0 * ktab_g1(k0, sigma, r) * sn[k0 * hp + j0] * in[((int64_t)k0 * hp + j1) * hp + j2];
+  const double n3 = (double)r * (double)r * (double)r;
+  table[e] = (float)(-2.0 / n3 / (2.0 * M_PI) * acc);
+}
+
+int build_point_source_table(int res, float sigma, float* table, void* scratch, hipStream_t stream) {
+  const size_t hp = (size_t)res / 2 + 1;
+  char* b = static_cast<char*>(scratch);
+  double* a1 = reinterpret_cast<double*>(b);
+  double* a2 = reinterpret_cast<double*>(b + align256(hp * hp * hp * 8));
+  double* cs = reinterpret_cast<double*>(b + 2 * align256(hp * hp * hp * 8));
+  double* sn = reinterpret_cast<double*>(b + 2 * align256(hp * hp * hp * 8) + align256(hp * hp * 8));
+  const int n2 = (int)((hp * hp + 255) / 256), n3 = (int)((hp * hp * hp + 255) / 256);
+  hipLaunchKernelGGL(k_ktab_trig, dim3(n2), dim3(256), 0, stream, cs, sn, res);
+  hipLaunchKernelGGL(k_ktab_pass1, dim3(n3), dim3(256), 0, stream, cs, a1, (double)sigma, res);
+  hipLaunchKernelGGL(k_ktab_pass2, dim3(n3), dim3(256), 0, stream, cs, a1, a2, (double)sigma, res);
+  hipLaunchKernelGGL(k_ktab_pass3, dim3(n3), dim3(256), 0, stream, sn, a2, table, (double)sigma, res);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
 // ---------------------------------------------------------------------------
@@ -2038,7 +2177,7 @@ __global__ __launch_bounds__(256) void k_bwd_point_finalize(const Batch<MAXJ> B)
     }
     return;
   }
-  b_bwd_point_finalize(w.part, sv.gradf, sv.sorted, w.bs, J.P, J.dpts, J.dnrm, bid);
+  b_bwd_point_finalize<RES>(w.part, sv.gradf, sv.sorted, w.bs, J.ktab, J.P, J.dpts, J.dnrm, bid);
 }
 
 // ---------------------------------------------------------------------------

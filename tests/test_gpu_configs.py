@@ -160,3 +160,26 @@ def test_c1_sphere_is_an_indicator(dev):
     inside, outside = chi[d < 0.3 - 3 / 32], chi[d > 0.3 + 3 / 32]
     assert -0.65 <= inside.mean() <= -0.50 and inside.std() < 0.03
     assert abs(outside.mean() - 0.5) < 0.01
+
+
+@pytest.mark.parametrize("res,which", [(128, "c4_sphere"), (64, "c4_torus"), (256, "c3")])
+def test_loss_correlated_with_chi(dev, res, which):
+    """Loss mean(chi^2), so G = 2 chi / N: the derivative through chi'(0,0,0)
+    (Eq. 4) puts a point source -Q delta_0 with Q = sum(G chi)/c into the
+    cotangent, about sqrt(N) times the rest of it in L2. Its response is
+    read at the points from the FP64-built table, so the gradients keep the
+    1e-4 bar (an FP32 transform of the spike gave 1.4e-4 at 128^3)."""
+    from paper_2106_03452_amd import function as F
+    if which == "c3":
+        sh = S.config_c3()
+    else:
+        kind = which.split("_")[1]
+        sh = next(s for s in S.config_c4() if s.res == res and s.kind == kind and s.P > 10000)
+    announce(f"loss mean(chi^2) res={res} {which} P={sh.P}")
+    chi, saved = F.forward(to_dev(sh.points, dev), to_dev(sh.normals, dev), res, sh.sigma)
+    dp, dn = F.backward(chi, saved, (2.0 * chi / chi.numel()).contiguous(), sh.P, res, sh.sigma)
+    ref, aux = oracle.forward(sh.points, sh.normals, res, sh.sigma)
+    dc_r, dn_r = oracle.backward(aux, 2.0 * ref / ref.size)
+    e_chi, e_dc, e_dn = max_rel(host(chi), ref), l2_rel(host(dp), dc_r), l2_rel(host(dn), dn_r)
+    print(f"mean(chi^2) {which} {res}^3: e_chi={e_chi:.3e} e_dpoints={e_dc:.3e} e_dnormals={e_dn:.3e}")
+    assert e_chi < 1e-5 and e_dc < 1e-4 and e_dn < 1e-4
