@@ -64,7 +64,8 @@ enum {
   PSR_EDEGENERATE = -3,   /* scale c is zero or non-finite (e.g. all normals zero); chi is NaN */
   PSR_EDEVICE = -4,       /* a HIP runtime call failed */
   PSR_ENOTREADY = -5,     /* reserved */
-  PSR_ENONFINITE = -6     /* a point coordinate or normal component is NaN or Inf; chi is NaN */
+  PSR_ENONFINITE = -6,    /* a point coordinate or normal component is NaN or Inf; chi is NaN */
+  PSR_ETOOBIG = -7        /* the problem exceeds a fixed limit of the entry point (see its comment) */
 };
 
 #define PSR_MIN_RES 8
@@ -187,6 +188,65 @@ int psr_debug_spectral(psr_ctx* ctx, const float* v, int res, float sigma, float
 int psr_debug_splat(psr_ctx* ctx, const float* points, const float* normals, int64_t npoints,
                     int res, float* v, void* saved, void* workspace, size_t workspace_bytes,
                     hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Marching Cubes on the indicator grid and its inverse-normal gradient
+ * (main Sec. 3.2: the mesh of chi by Marching Cubes, Lorensen and Cline 1987;
+ * main Eq. 6: dp_mesh/dchi = -n_mesh).
+ *
+ * The surface is the level chi = iso (main Eq. 2 makes the mean of chi at
+ * the input points 0, so iso = 0 passes through them). The grid is sampled as
+ * an image volume: cells (j, j+1) along each axis for j in [0, res-2], vertex
+ * j at position j/res. A grid edge whose ends lie on different sides of the
+ * level (inside = chi < iso) carries one mesh vertex at
+ * t = (chi_a - iso)/(chi_a - chi_b) along it; its normal is the periodic
+ * central-difference gradient of chi interpolated with the same t and
+ * normalised (it points to chi > iso, outward). Vertices are numbered by
+ * global edge id 3 * (row-major index of the edge's lower end) + axis;
+ * triangles by cell (row-major), then case-table order, counter-clockwise
+ * seen from outside. Faces with four crossing edges cut each inside corner
+ * off on its own, so the mesh is closed and edge-manifold wherever the
+ * level set stays inside the grid.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of the state buffer for a res^3 grid (host-only query): per-vertex
+ * base indices (4 res^3 bytes), per-workgroup counts and a header. */
+int psr_mc_state_bytes(int res, size_t* bytes);
+
+/* Mesh of chi ([res]^3 float32, device) at the level iso. Writes up to vcap
+ * vertices (verts, normals: [vcap][3] float32; edges: [vcap] int32 global
+ * edge ids, may be NULL) and up to tcap triangles (tris: [tcap][3] int32
+ * vertex indices); `state` (psr_mc_state_bytes, caller-owned, 256-byte
+ * aligned) receives the totals and the vertex map that the backward needs.
+ * Stream-ordered; the totals are read with psr_mc_counts. If a total exceeds
+ * its capacity the output is truncated (triangles may then index vertices
+ * beyond vcap): call again with larger buffers. */
+int psr_marching_cubes(psr_ctx* ctx, const float* chi, int res, float iso, float* verts, float* normals,
+                       int32_t* edges, int64_t vcap, int32_t* tris, int64_t tcap, void* state,
+                       hipStream_t stream);
+
+/* Synchronises `stream` and reads the totals of the last psr_marching_cubes
+ * into *nverts and *ntris (either may be NULL); *status (may be NULL) is
+ * PSR_OK, or PSR_ETOOBIG when the mesh has 2^29 vertices or more (the vertex
+ * map cannot hold them; the output is then not valid). */
+int psr_mc_counts(const void* state, hipStream_t stream, int64_t* nverts, int64_t* ntris, int* status);
+
+/* Gradient of a loss through the mesh vertices back to the grid (main Eq. 6):
+ * with g_v = -(dL/dp_v . n_v) for vertex v on the grid edge (a, b) at t,
+ * dchi[a] += (1 - t) g_v and dchi[b] += t g_v; every grid value of dchi
+ * ([res]^3 float32) is written. `chi`, `iso` and `state` are those of the
+ * forward, unchanged; normals are the forward's, dverts = dL/dverts
+ * ([nverts][3]); vertices at or beyond nverts contribute nothing. If `state`
+ * was made for another res or iso, dchi is filled with NaN. */
+int psr_marching_cubes_backward(psr_ctx* ctx, const float* chi, int res, float iso, const void* state,
+                                const float* normals, const float* dverts, int64_t nverts, float* dchi,
+                                hipStream_t stream);
+
+/* Test hook (host only): the case table the kernels use. ntri[256]: triangles
+ * per sign pattern (bit k = corner k inside, corner k at offset (k&1,
+ * (k>>1)&1, k>>2)); edges[256][15]: their local edge ids, edge 4a + u + 2v
+ * along axis a from the corner whose other two coordinates are (u, v). */
+int psr_mc_case_table(int8_t* ntri, int8_t* edges);
 
 /* Stage timers (enabled with psr_ctx_set(ctx, "timers", 1)). Synchronises all
  * recorded events and returns, per stage id in [0, n), the summed duration in

@@ -25,6 +25,7 @@ PSR_EDEGENERATE = -3
 PSR_EDEVICE = -4
 PSR_ENOTREADY = -5
 PSR_ENONFINITE = -6
+PSR_ETOOBIG = -7
 
 
 class PSRError(RuntimeError):
@@ -75,6 +76,11 @@ def _declare(L):
         "psr_run_batched": ([vp, i32, P(PsrJob), vp], i32),
         "psr_debug_spectral": ([vp, vp, i32, f32, vp, vp, sz, vp], i32),
         "psr_debug_splat": ([vp, vp, vp, i64, i32, vp, vp, vp, sz, vp], i32),
+        "psr_mc_state_bytes": ([i32, P(sz)], i32),
+        "psr_marching_cubes": ([vp, vp, i32, f32, vp, vp, vp, i64, vp, i64, vp, vp], i32),
+        "psr_mc_counts": ([vp, vp, P(i64), P(i64), P(i32)], i32),
+        "psr_marching_cubes_backward": ([vp, vp, i32, f32, vp, vp, vp, i64, vp, vp], i32),
+        "psr_mc_case_table": ([vp, vp], i32),
         "psr_ctx_stage_times": ([vp, P(f64), P(i64), i32], i32),
         "psr_ctx_reset_timers": ([vp], i32),
         "psr_stage_name": ([i32], ctypes.c_char_p),

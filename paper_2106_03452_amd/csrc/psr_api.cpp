@@ -11,6 +11,7 @@
 
 #include "psr.h"
 #include "psr_internal.h"
+#include "psr_mc.h"
 
 namespace psr {
 
@@ -199,6 +200,7 @@ const char* psr_strerror(int code) {
     case PSR_EDEVICE: return "HIP runtime error";
     case PSR_ENOTREADY: return "not ready";
     case PSR_ENONFINITE: return "non-finite point coordinate";
+    case PSR_ETOOBIG: return "problem too large for this entry point";
     default: return "unknown status code";
   }
 }
@@ -431,6 +433,53 @@ int psr_debug_splat(psr_ctx* ctx, const float* points, const float* normals, int
   psr::JobArg j = make_job(points, normals, npoints, 0.0f, nullptr, saved, workspace);
   j.aux_out = v;
   return psr::run_debug_splat(x, res, j);
+}
+
+int psr_mc_state_bytes(int res, size_t* bytes) {
+  if (!bytes || !valid_res(res)) return PSR_EINVAL;
+  *bytes = psr::mc::state_layout(res).total;
+  return PSR_OK;
+}
+
+int psr_marching_cubes(psr_ctx* ctx, const float* chi, int res, float iso, float* verts, float* normals,
+                       int32_t* edges, int64_t vcap, int32_t* tris, int64_t tcap, void* state,
+                       hipStream_t stream) {
+  if (!ctx || !chi || !state || !valid_res(res) || !std::isfinite(iso) || vcap < 0 || tcap < 0) return PSR_EINVAL;
+  if ((vcap > 0 && (!verts || !normals)) || (tcap > 0 && !tris)) return PSR_EINVAL;
+  if (!aligned(state, 256) || !aligned(chi, 4)) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  psr::mc::McOut out{verts, normals, edges, tris, vcap, tcap};
+  return psr::mc::run_forward(res, chi, iso, psr::mc::state_view(state, res), out, stream) ? PSR_EDEVICE : PSR_OK;
+}
+
+int psr_mc_counts(const void* state, hipStream_t stream, int64_t* nverts, int64_t* ntris, int* status) {
+  if (!state) return PSR_EINVAL;
+  if (hipStreamSynchronize(stream) != hipSuccess) return PSR_EDEVICE;
+  psr::mc::McHeader h;
+  if (hipMemcpy(&h, state, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return PSR_EDEVICE;
+  if (nverts) *nverts = h.nv;
+  if (ntris) *ntris = h.nt;
+  if (status) *status = h.status ? PSR_ETOOBIG : PSR_OK;
+  return PSR_OK;
+}
+
+int psr_marching_cubes_backward(psr_ctx* ctx, const float* chi, int res, float iso, const void* state,
+                                const float* normals, const float* dverts, int64_t nverts, float* dchi,
+                                hipStream_t stream) {
+  if (!ctx || !chi || !state || !dchi || !valid_res(res) || !std::isfinite(iso) || nverts < 0) return PSR_EINVAL;
+  if (nverts > 0 && (!normals || !dverts)) return PSR_EINVAL;
+  if (!aligned(state, 256)) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  return psr::mc::run_backward(res, chi, iso, psr::mc::state_view(const_cast<void*>(state), res), normals, dverts,
+                               nverts, dchi, stream)
+             ? PSR_EDEVICE
+             : PSR_OK;
+}
+
+int psr_mc_case_table(int8_t* ntri, int8_t* edges) {
+  if (!ntri && !edges) return PSR_EINVAL;
+  psr::mc::case_table(ntri, edges);
+  return PSR_OK;
 }
 
 int psr_ctx_stage_times(psr_ctx* ctx, double* ms, int64_t* counts, int n) {

@@ -62,3 +62,19 @@ def test_null_arguments_rejected_without_device_work(L):
     assert L.psr_run_batched(None, 1, None, None) == _lib.PSR_EINVAL
     assert L.psr_debug_spectral(None, None, 64, 2.0, None, None, 0, None) == _lib.PSR_EINVAL
     assert L.psr_saved_status(None, None, None) == _lib.PSR_EINVAL
+
+
+def test_mc_case_table_matches_the_oracle(L):
+    """The library builds its Marching Cubes table at compile time from the
+    same face rule the oracle implements in Python: both must agree entry by
+    entry (host only, no GPU)."""
+    import ctypes
+    from oracle import mc
+    ntri = (ctypes.c_int8 * 256)()
+    edges = (ctypes.c_int8 * (256 * 15))()
+    L.psr_mc_case_table.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert L.psr_mc_case_table(ctypes.cast(ntri, ctypes.c_void_p), ctypes.cast(edges, ctypes.c_void_p)) == 0
+    table = mc.case_table()
+    for c in range(256):
+        got = [tuple(edges[c * 15 + 3 * i: c * 15 + 3 * i + 3]) for i in range(ntri[c])]
+        assert got == [tuple(t) for t in table[c]], c
