@@ -110,6 +110,27 @@ int psr_forward(psr_ctx* ctx, const float* points, const float* normals, int64_t
                 int res, float sigma, float* chi, void* saved, void* workspace,
                 size_t workspace_bytes, hipStream_t stream);
 
+/* Forward solve that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc). Same arguments and result as psr_forward without
+ * `saved` and `workspace`: both are carved from one static device array of
+ * PSR_STATIC_SCRATCH_BYTES per GPU (64 MiB, held from library load until the
+ * process ends), whose address the context takes at psr_ctx_create. The
+ * call makes no hipMalloc, hipFree or other allocating call.
+ *   Limit: psr_saved_bytes(res, npoints) + psr_workspace_bytes(res, npoints)
+ *   must not exceed PSR_STATIC_SCRATCH_BYTES (res 128 with up to 57,036
+ *   points, res 64 with up to 216,432, res 32 with up to 236,622; no res of
+ *   256 or more fits); larger problems return PSR_ETOOBIG and launch nothing.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (each call re-initialises what it reads): calls that overlap on
+ * one GPU (two streams, or two threads) race and must be serialised by the
+ * caller. There is no backward for this call (its state is not kept), and
+ * the status of the solve is not reported: a degenerate or non-finite input
+ * gives a NaN grid. */
+#define PSR_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int psr_forward_static(psr_ctx* ctx, const float* points, const float* normals, int64_t npoints, int res,
+                       float sigma, float* chi, hipStream_t stream);
+
 /* Backward (adjoint) of psr_forward: the gradient of a loss L(chi) with
  * respect to the oriented points that main Sec. 3.1 asks of the solver (the
  * paper differentiates Eqs. 3-4 by autograd; here the adjoint is written out:

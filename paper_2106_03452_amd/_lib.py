@@ -69,6 +69,7 @@ def _declare(L):
         "psr_workspace_bytes": ([i32, i64, i32, P(sz)], i32),
         "psr_saved_bytes": ([i32, i64, P(sz)], i32),
         "psr_forward": ([vp, vp, vp, i64, i32, f32, vp, vp, vp, sz, vp], i32),
+        "psr_forward_static": ([vp, vp, vp, i64, i32, f32, vp, vp], i32),
         "psr_backward": ([vp, i64, i32, f32, vp, vp, vp, vp, vp, vp, sz, vp], i32),
         "psr_ctx_prepare": ([vp, i32, f32, vp], i32),
         "psr_saved_status": ([vp, vp, P(i32)], i32),

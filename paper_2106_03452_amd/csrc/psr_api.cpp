@@ -86,6 +86,8 @@ struct psr_ctx {
   double m = 0.5;
   int reading = 0;
   psr::Timers* timers = nullptr;
+  // device address of this device's static scratch array (psr_forward_static)
+  void* scratch = nullptr;
   // point-source tables of the backward, one per (res, sigma), kept until
   // the context is destroyed
   struct KTab {
@@ -233,6 +235,9 @@ int psr_ctx_create(psr_ctx** out, int device) {
     delete c;
     return PSR_EDEVICE;
   }
+  // this device's copy of the static scratch array (device current here);
+  // without it only psr_forward_static is unavailable
+  if (psr::static_scratch_address(&c->scratch) != 0) c->scratch = nullptr;
   *out = c;
   return PSR_OK;
 }
@@ -313,6 +318,22 @@ int psr_forward(psr_ctx* ctx, const float* points, const float* normals, int64_t
   DeviceGuard g(ctx->device);
   psr::Exec x = make_exec(ctx, stream);
   psr::JobArg j = make_job(points, normals, npoints, sigma, chi, saved, workspace);
+  return psr::run_jobs(x, res, &j, 1, psr::RUN_FORWARD);
+}
+
+int psr_forward_static(psr_ctx* ctx, const float* points, const float* normals, int64_t npoints, int res,
+                       float sigma, float* chi, hipStream_t stream) {
+  if (!ctx || !points || !normals || !chi) return PSR_EINVAL;
+  if (!valid_res(res) || !valid_P(npoints) || !(sigma >= 0.0f) || !std::isfinite(sigma)) return PSR_EINVAL;
+  if (!aligned(chi, 16)) return PSR_EINVAL;
+  const size_t sv_bytes = psr::saved_layout(res, npoints).total;  // a multiple of 256
+  if (sv_bytes + psr::ws_layout(res, npoints).total > psr::kStaticScratchBytes) return PSR_ETOOBIG;
+  if (!ctx->scratch) return PSR_EDEVICE;
+  DeviceGuard g(ctx->device);
+  psr::Exec x = make_exec(ctx, stream);
+  x.timers = nullptr;  // no event creation on this path
+  char* base = static_cast<char*>(ctx->scratch);
+  psr::JobArg j = make_job(points, normals, npoints, sigma, chi, base, base + sv_bytes);
   return psr::run_jobs(x, res, &j, 1, psr::RUN_FORWARD);
 }
 

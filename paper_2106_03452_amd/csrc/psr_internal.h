@@ -236,6 +236,13 @@ __host__ __device__ inline size_t ktab_scratch_bytes(int res) {
 // `stream`. Returns 0 or -4 (launch failure).
 int build_point_source_table(int res, float sigma, float* table, void* scratch, hipStream_t stream);
 
+// The allocation-free forward (psr_forward_static) carves its workspace and
+// saved state out of one static device array of this size per GPU.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+// Device address of that array on the current device (hipGetSymbolAddress);
+// 0 on success, -4 on failure.
+int static_scratch_address(void** out);
+
 // Run forward and/or backward for n jobs of one resolution.
 int run_jobs(Exec& x, int res, const JobArg* jobs, int n, int what);
 int run_debug_spectral(Exec& x, int res, const JobArg& job);

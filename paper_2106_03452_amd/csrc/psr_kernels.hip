@@ -2181,6 +2181,20 @@ __global__ __launch_bounds__(256) void k_bwd_point_finalize(const Batch<MAXJ> B)
 }
 
 // ---------------------------------------------------------------------------
+// Scratch of the allocation-free forward (psr_forward_static): the workspace
+// and the saved state of one solve, in one static array per GPU. Host code
+// must not pass the array's name to a kernel (on the host it only stands for
+// the symbol); the library takes its device address once per device at
+// context creation and passes that.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+int static_scratch_address(void** out) {
+  *out = nullptr;
+  return hipGetSymbolAddress(out, HIP_SYMBOL(scratch)) == hipSuccess ? 0 : -4;
+}
+
+// ---------------------------------------------------------------------------
 // host-side launch sequences
 // ---------------------------------------------------------------------------
 static inline int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
