@@ -10,8 +10,12 @@ the paper and by mathematics (worked splat example, brute-force trilinear
 weights, naive DFT, single-Fourier-mode closed forms, a dense FFT-free spectral
 solve, adjoint dot products, finite differences, invariants).
 The Marching Cubes layer and its inverse-normal gradient (main Sec. 3.2,
-Eq. 6) are in ``oracle.mc``, pinned by ``tests/test_mc_oracle.py``.
+Eq. 6) are in ``oracle.mc``, pinned by ``tests/test_mc_oracle.py``; the
+pieces of the optimisation loop (mesh sampling, Chamfer loss, connected
+components for the resampling) in ``oracle.opt``, pinned by
+``tests/test_opt_oracle.py``.
 """
 from .dpsr import *  # noqa: F401,F403
 from . import dpsr  # noqa: F401
 from . import mc  # noqa: F401
+from . import opt  # noqa: F401
