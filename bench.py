@@ -154,10 +154,15 @@ KERNEL_STAGES = [
 ]
 
 
+SOLVER_SOURCES = ["fft_device.h", "psr_geometry.h", "psr_internal.h", "psr_kernels.hip"]
+
+
 def kernel_source_hash() -> str:
+    """Hash of the sources the solver's kernels are built from (the counters
+    of profiles/ stay valid while it is unchanged)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2106_03452_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in SOLVER_SOURCES:
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(name.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -440,6 +445,54 @@ def serve_mode(dev, torch, n_requests, levels=(0.5, 0.8, 1.0, 1.5)):
     return out
 
 
+def mc_bytes(r: int, nv: int, nt: int, backward: bool = False) -> int:
+    """Algorithmic bytes of the Marching Cubes layer: the grid read once and
+    the mesh written once (positions, normals, edge ids: 28 B per vertex;
+    triangles 12 B), or for the backward the grid read, dL/dchi written and
+    dL/dverts and the normals read (24 B per vertex)."""
+    n = r ** 3
+    return 8 * n + 24 * nv if backward else 4 * n + 28 * nv + 12 * nt
+
+
+def marching_cubes_leg(dev, torch, chi, steps=20, warmup=3):
+    """Marching Cubes of a solver output (level 0) and its backward, timed
+    with HIP events around the library calls on the current stream."""
+    import ctypes
+    from paper_2106_03452_amd import _lib
+    from paper_2106_03452_amd import mesh as M
+    L = _lib.lib()
+    ctx = _lib.context(0)
+    m = M.marching_cubes(chi)
+    r = int(chi.shape[0])
+    nv, nt = int(m.verts.shape[0]), int(m.faces.shape[0])
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    verts = torch.empty((nv, 3), dtype=torch.float32, device=dev)
+    nrm = torch.empty((nv, 3), dtype=torch.float32, device=dev)
+    edges = torch.empty((nv,), dtype=torch.int32, device=dev)
+    tris = torch.empty((nt, 3), dtype=torch.int32, device=dev)
+    state = torch.empty_like(m.state)
+    dv = torch.randn((nv, 3), dtype=torch.float32, device=dev)
+    dchi = torch.empty_like(chi)
+
+    def fwd():
+        _lib.check(L.psr_marching_cubes(ctx.handle, p(chi), r, 0.0, p(verts), p(nrm), p(edges), nv, p(tris), nt,
+                                        p(state), st), "psr_marching_cubes")
+
+    def bwd():
+        _lib.check(L.psr_marching_cubes_backward(ctx.handle, p(chi), r, 0.0, p(state), p(nrm), p(dv), nv, p(dchi),
+                                                 st), "psr_marching_cubes_backward")
+    out = {"res": r, "vertices": nv, "triangles": nt}
+    for name, fn, back in (("forward", fwd, False), ("backward", bwd, True)):
+        for _ in range(warmup):
+            fn()
+        ms = step_times(fn, steps, torch)["median_ms"]
+        b = mc_bytes(r, nv, nt, back)
+        out[name] = {"ms": ms, "algorithmic_bytes": b, "GBs": round(b / (ms * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def timed(step, steps, warmup, torch):
     for _ in range(warmup):
         step()
@@ -464,6 +517,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=600,
                     help="requests of the compact serving leg of the default run (levels 1.0 and 1.5 x lambda_seq)")
     ap.add_argument("--no-serve", action="store_true", help="skip the compact serving leg")
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "mc"], default="c3",
+                    help="profiling runs: c3 = the headline line (default); c2 = only the 128^3 fwd+bwd steps; "
+                         "c4 = only the 64-shape batch; mc = only Marching Cubes of the 256^3 solve")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (scale reference for HBM counters)")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -503,6 +559,18 @@ def main():
     from paper_2106_03452_amd import function as F
 
     ctx = _lib.context(0)
+    if args.workload != "c3":
+        # profiling runs of one secondary workload (no JSON contract line)
+        if args.workload == "c2":
+            b2 = prepare(S.config_c2(), dev, torch, F)
+            dt = timed(make_step(b2, ctx), args.steps, args.warmup, torch)
+            print(json.dumps({"workload": "c2", "ms_per_step": round(dt / args.steps * 1e3, 4)}), flush=True)
+        elif args.workload == "c4":
+            print(json.dumps({"workload": "c4", **batch_c4(dev, torch, args.steps, args.warmup)}), flush=True)
+        else:
+            b3 = prepare(S.config_c3(), dev, torch, F)
+            print(json.dumps({"workload": "mc", **marching_cubes_leg(dev, torch, b3["chi"], args.steps)}), flush=True)
+        return
     shape = S.config_c3()
     b = prepare(shape, dev, torch, F)
     r, P = b["r"], b["P"]
@@ -611,6 +679,7 @@ def main():
                                     "ms": round(d1 / (args.steps * 10) * 1e3, 4)}
         del b1
         secondary["batch_c4"] = batch_c4(dev, torch)
+        secondary["marching_cubes_256"] = marching_cubes_leg(dev, torch, b["chi"])
         if not args.no_serve:
             secondary["serve_c5"] = serve_mode(dev, torch, args.serve_requests, levels=(1.0, 1.5))
 

@@ -1836,65 +1836,68 @@ __device__ __forceinline__ float ktab_at(const float* __restrict__ kt, int d, in
 // alpha grad chi'(c_i) (the mean term); then the point source -Q delta_0 of
 // the cotangent, applied here from the table: -Q K_d gathered at the point
 // into dn_d, and -Q sum_d n_d K_d through the weight gradient into dc.
+// Eight lanes per point, one per corner o: each reads its corner's three
+// table values and (lanes 0-5) two of the twelve partials, and the lanes'
+// shares are summed with shuffles in a fixed order.
+constexpr int kFinalLanes = 8;
+
 template <int RES>
 __device__ __forceinline__ void b_bwd_point_finalize(const float4* __restrict__ part, const float4* __restrict__ gradf,
                                      const PointRec* __restrict__ sorted, const BwdScalars* __restrict__ bs,
                                      const float* __restrict__ ktab, int64_t npoints, float* __restrict__ dpoints,
                                      float* __restrict__ dnormals, int bid) {
-  const int64_t s = (int64_t)bid * blockDim.x + threadIdx.x;
-  if (s >= npoints) return;
+  const int64_t s = ((int64_t)bid * blockDim.x + threadIdx.x) / kFinalLanes;
+  const int o = threadIdx.x % kFinalLanes;
+  const bool live = s < npoints;  // the 8 lanes of a point agree (whole groups only)
+  const int64_t sr = live ? s : 0;
   float4 p0, p1;
-  load_rec(sorted, s, p0, p1);
+  load_rec(sorted, sr, p0, p1);
   const float nv[3] = {p1.x, p1.y, p1.z};
   float dn[3] = {0.0f, 0.0f, 0.0f}, dc[3] = {0.0f, 0.0f, 0.0f};
+  // partials (c, slot) = (o / 2, 2 (o % 2) + h) for lanes 0-5: channel c, two slots each
+  if (o < 6 && live) {
+    const int c = o >> 1;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
-#pragma unroll
-    for (int slot = 0; slot < 4; ++slot) {
-      const float4 q = part[(c * 4 + slot) * npoints + s];
+    for (int h = 0; h < 2; ++h) {
+      const float4 q = part[(c * 4 + 2 * (o & 1) + h) * npoints + s];
       dn[c] += q.x;
-      g0 += q.y;
-      g1 += q.z;
-      g2 += q.w;
+      dc[0] += nv[c] * q.y;
+      dc[1] += nv[c] * q.z;
+      dc[2] += nv[c] * q.w;
     }
-    dc[0] += nv[c] * g0;
-    dc[1] += nv[c] * g1;
-    dc[2] += nv[c] * g2;
   }
+  {
+    const float mq = -bs->q;
+    const uint32_t bb = __float_as_uint(p0.w);
+    const int o0 = o & 1, o1 = (o >> 1) & 1, o2 = o >> 2;
+    const int v0 = ((bb & 1023) + o0) & (RES - 1), v1 = (((bb >> 10) & 1023) + o1) & (RES - 1),
+              v2 = ((bb >> 20) + o2) & (RES - 1);
+    const float w0 = o0 ? p0.x : 1.0f - p0.x, w1 = o1 ? p0.y : 1.0f - p0.y, w2 = o2 ? p0.z : 1.0f - p0.z;
+    const float k0 = ktab_at<RES>(ktab, 0, v0, v1, v2), k1 = ktab_at<RES>(ktab, 1, v0, v1, v2),
+                k2 = ktab_at<RES>(ktab, 2, v0, v1, v2);
+    const float w = (w0 * w1) * w2;
+    const float nk = mq * (nv[0] * k0 + nv[1] * k1 + nv[2] * k2);
+    dn[0] += mq * (w * k0);
+    dn[1] += mq * (w * k1);
+    dn[2] += mq * (w * k2);
+    dc[0] += (float)RES * ((o0 ? 1.0f : -1.0f) * (w1 * w2) * nk);
+    dc[1] += (float)RES * ((o1 ? 1.0f : -1.0f) * (w0 * w2) * nk);
+    dc[2] += (float)RES * ((o2 ? 1.0f : -1.0f) * (w0 * w1) * nk);
+  }
+#pragma unroll
+  for (int d = 1; d < kFinalLanes; d <<= 1) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      dn[k] += __shfl_xor(dn[k], d, kFinalLanes);
+      dc[k] += __shfl_xor(dc[k], d, kFinalLanes);
+    }
+  }
+  if (!live || o != 0) return;
   const float alpha = bs->alpha;
   const float4 g = gradf[s];
   dc[0] += alpha * g.x;
   dc[1] += alpha * g.y;
   dc[2] += alpha * g.z;
-  {
-    const float mq = -bs->q;
-    const uint32_t bb = __float_as_uint(p0.w);
-    const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
-    const float f[3] = {p0.x, p0.y, p0.z};
-    float kn[3] = {0.0f, 0.0f, 0.0f}, kc[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      const int o0 = o & 1, o1 = (o >> 1) & 1, o2 = o >> 2;
-      const int v0 = (b0 + o0) & (RES - 1), v1 = (b1 + o1) & (RES - 1), v2 = (b2 + o2) & (RES - 1);
-      const float w0 = o0 ? f[0] : 1.0f - f[0], w1 = o1 ? f[1] : 1.0f - f[1], w2 = o2 ? f[2] : 1.0f - f[2];
-      const float k0 = ktab_at<RES>(ktab, 0, v0, v1, v2), k1 = ktab_at<RES>(ktab, 1, v0, v1, v2),
-                  k2 = ktab_at<RES>(ktab, 2, v0, v1, v2);
-      const float w = (w0 * w1) * w2;
-      kn[0] += w * k0;
-      kn[1] += w * k1;
-      kn[2] += w * k2;
-      const float nk = nv[0] * k0 + nv[1] * k1 + nv[2] * k2;
-      kc[0] += (o0 ? 1.0f : -1.0f) * (w1 * w2) * nk;
-      kc[1] += (o1 ? 1.0f : -1.0f) * (w0 * w2) * nk;
-      kc[2] += (o2 ? 1.0f : -1.0f) * (w0 * w1) * nk;
-    }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      dn[d] += mq * kn[d];
-      dc[d] += mq * ((float)RES * kc[d]);
-    }
-  }
   const int64_t i = (int64_t)__float_as_uint(p1.w);
   if (dpoints) {
     dpoints[3 * i + 0] = dc[0];
@@ -2169,9 +2172,9 @@ template <int RES, int MAXJ>
 __global__ __launch_bounds__(256) void k_bwd_point_finalize(const Batch<MAXJ> B) {
   PSR_JOB(RES);
   if (saved_mismatch<RES>(sv.hdr, J.P)) {
-    const int64_t s = (int64_t)bid * blockDim.x + threadIdx.x;
+    const int64_t s = ((int64_t)bid * blockDim.x + threadIdx.x) / kFinalLanes;
     const float nan = __int_as_float(0x7fc00000);
-    for (int k = 0; k < 3 && s < J.P; ++k) {
+    for (int k = 0; k < 3 && s < J.P && threadIdx.x % kFinalLanes == 0; ++k) {
       if (J.dpts) J.dpts[3 * s + k] = nan;
       if (J.dnrm) J.dnrm[3 * s + k] = nan;
     }
@@ -2329,7 +2332,8 @@ static int seq_backward(Exec& x, const JobArg* J, int n) {
     x.end(STAGE_B5);
   }
   x.begin(STAGE_BWD_FINAL);
-  rc |= launch<MAXJ>(x, k_bwd_point_finalize<RES, MAXJ>, 256, J, n, [](const JobArg& a) { return nblk(a.P, 256); });
+  rc |= launch<MAXJ>(x, k_bwd_point_finalize<RES, MAXJ>, 256, J, n,
+                     [](const JobArg& a) { return nblk(a.P * kFinalLanes, 256); });
   x.end(STAGE_BWD_FINAL);
   return rc ? -4 : 0;
 }

@@ -266,6 +266,12 @@ class GpuBackend:
 
     def alloc_slot(self, res, pmax):
         torch = self.torch
+        if hasattr(self, "ctx"):
+            # the backward's point-source table of this size, built once now
+            # rather than inside a batch
+            self._lib.check(self._lib.lib().psr_ctx_prepare(
+                self.ctx.handle, int(res), float(getattr(self, "sigma", 2.0)),
+                ctypes.c_void_p(torch.cuda.current_stream(self.dev).cuda_stream)), "psr_ctx_prepare")
         try:
             return dict(
                 ws=torch.empty(self._lib.workspace_bytes(res, pmax), dtype=torch.uint8, device=self.dev),
