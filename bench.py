@@ -493,6 +493,61 @@ def marching_cubes_leg(dev, torch, chi, steps=20, warmup=3):
     return out
 
 
+def optimisation_leg(dev, torch, iters=40, npoints=20000):
+    """The optimisation loop of main Sec. 3.2 on a synthetic target (a rotated
+    torus, 20k points): ms per iteration (solve, Marching Cubes, sampling,
+    Chamfer, every backward and the Adam step) at each grid size of the
+    paper's schedule, a resampling from the largest component included every
+    `iters // 2` iterations, and the whole schedule's time from them."""
+    import psr_synth as S
+    from paper_2106_03452_amd import optimize as O
+    target = torch.from_numpy(S.tiny_case(8, 256, npoints, kind="torus").points).to(dev)
+    out = {"workload": f"{npoints}-point torus target, {npoints} source points and samples, "
+                       f"{iters} iterations per grid size", "ms_per_iter": {}}
+    for lev in O.PAPER_SCHEDULE:
+        r = O.optimise(target, [O.Level(lev.res, lev.sigma, iters)], npoints=npoints, resample_every=iters // 2,
+                       log_every=0)
+        out["ms_per_iter"][str(lev.res)] = round(r.ms_per_iter[lev.res], 3)
+    full = sum(out["ms_per_iter"][str(l.res)] * l.iters for l in O.PAPER_SCHEDULE) / 1e3
+    out["schedule_s"] = round(full, 2)
+    out["schedule"] = "32^3 x1000, 64^3 x1000, 128^3 x1000, 256^3 x200 (sigma 2, 2, 3, 3)"
+    out["paper_gtx1080ti_s"] = "326-380 per object (its Table: Thingi10K, SRB, D-FAUST)"
+    return out
+
+
+def training_leg(dev, torch, batch=8, steps=10, warmup=3, res=128):
+    """One DPSR-loss training step (main Sec. 3.3): the point network, the
+    batched solve of all shapes, the MSE against the ground-truth grids,
+    every backward and the Adam step; 3,000 noisy input points per shape and
+    k = 7 offsets (21,000 oriented points per shape) at 128^3."""
+    import numpy as np
+    import psr_synth as S
+    from paper_2106_03452_amd import function as F
+    from paper_2106_03452_amd import learn
+    rng = np.random.default_rng(7)
+    c_in, gt = [], []
+    for _ in range(batch):
+        sh = S.random_shape(rng, res, 20000)
+        c_in.append(sh.points[:3000] + rng.normal(0, 0.005, (3000, 3)).astype(np.float32))
+        chi, _ = F.forward(torch.from_numpy(sh.points).to(dev), torch.from_numpy(sh.normals).to(dev), res, 2.0)
+        gt.append(chi)
+    c = torch.from_numpy(np.stack(c_in)).to(dev)
+    torch.manual_seed(0)
+    model = learn.OffsetNormalNet(k=7).to(dev)
+    opt = torch.optim.Adam(model.parameters(), lr=1e-4)
+    for _ in range(warmup):
+        learn.train_step(model, opt, c, gt, res)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss = learn.train_step(model, opt, c, gt, res)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    return {"workload": f"batch of {batch} shapes, 3,000 input points x 7 offsets, {res}^3, sigma 2",
+            "ms_per_step": round(ms, 3), "shapes_per_s": round(batch / ms * 1e3, 1), "loss": float(loss),
+            "paper_context": "about 0.58 s per step of batch 32 on 2 GTX 1080Ti (2 days for 300k steps, whole model)"}
+
+
 def timed(step, steps, warmup, torch):
     for _ in range(warmup):
         step()
@@ -517,6 +572,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=600,
                     help="requests of the compact serving leg of the default run (levels 1.0 and 1.5 x lambda_seq)")
     ap.add_argument("--no-serve", action="store_true", help="skip the compact serving leg")
+    ap.add_argument("--no-loops", action="store_true", help="skip the optimisation-loop and training-step legs")
     ap.add_argument("--workload", choices=["c3", "c2", "c4", "mc"], default="c3",
                     help="profiling runs: c3 = the headline line (default); c2 = only the 128^3 fwd+bwd steps; "
                          "c4 = only the 64-shape batch; mc = only Marching Cubes of the 256^3 solve")
@@ -680,6 +736,9 @@ def main():
         del b1
         secondary["batch_c4"] = batch_c4(dev, torch)
         secondary["marching_cubes_256"] = marching_cubes_leg(dev, torch, b["chi"])
+        if not args.no_loops:
+            secondary["optimisation_loop"] = optimisation_leg(dev, torch)
+            secondary["training_step_128"] = training_leg(dev, torch)
         if not args.no_serve:
             secondary["serve_c5"] = serve_mode(dev, torch, args.serve_requests, levels=(1.0, 1.5))
 

@@ -177,10 +177,15 @@ int psr_saved_scalars(const void* saved, hipStream_t stream, double* mean, doubl
                       double* scale, double* chi0);
 
 /* One solve of a batch. Inputs/outputs as in psr_forward/psr_backward.
- * `dchi` NULL = forward only; otherwise the backward runs right after the
- * forward and writes dpoints/dnormals (either may be NULL). `workspace` and
- * `saved` are per job and must not overlap between jobs. `status` is unused
- * by the library (kept for callers). */
+ * With stages = PSR_JOB_FORWARD (0): `dchi` NULL = forward only; otherwise the
+ * backward runs right after the forward and writes dpoints/dnormals (either
+ * may be NULL). With stages = PSR_JOB_BACKWARD: only the backward runs, from
+ * the chi and saved state that an earlier forward of this job left (same
+ * npoints, res, sigma; points and normals may be NULL), so that an autograd
+ * caller can batch its forwards and, later, its backwards. `workspace` and
+ * `saved` are per job and must not overlap between jobs. */
+#define PSR_JOB_FORWARD 0
+#define PSR_JOB_BACKWARD 2
 typedef struct psr_job {
   const float* points;
   const float* normals;
@@ -194,10 +199,13 @@ typedef struct psr_job {
   float* dnormals;
   void* workspace;
   size_t workspace_bytes;
+  int32_t stages;  /* PSR_JOB_FORWARD or PSR_JOB_BACKWARD */
+  int32_t reserved;
 } psr_job;
 
 /* Run `njobs` independent solves with one launch per pipeline stage for the
- * whole batch (jobs may mix resolutions and point counts). Stream-ordered. */
+ * whole batch (jobs may mix resolutions, point counts and stages): the batched
+ * form of psr_forward/psr_backward. Stream-ordered. */
 int psr_run_batched(psr_ctx* ctx, int njobs, const psr_job* jobs, hipStream_t stream);
 
 /* Test hooks. psr_debug_spectral runs only the spectral solve on a given
@@ -262,6 +270,72 @@ int psr_mc_counts(const void* state, hipStream_t stream, int64_t* nverts, int64_
 int psr_marching_cubes_backward(psr_ctx* ctx, const float* chi, int res, float iso, const void* state,
                                 const float* normals, const float* dverts, int64_t nverts, float* dchi,
                                 hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * The optimisation-based reconstruction loop around the solver (main Sec.
+ * 3.2): points sampled on the mesh (the p_mesh of main Eq. 5), the
+ * bidirectional Chamfer loss of Eq. 5 against a target cloud, and the mesh's
+ * connected components for the resampling from the largest one (main Sec.
+ * 3.2, "Resampling"). All arrays are device memory; vertices [n][3] float32,
+ * faces [n][3] int32.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of the sampling workspace for a mesh of nfaces triangles (host only). */
+int psr_mesh_sample_workspace_bytes(int64_t nfaces, size_t* bytes);
+
+/* nsamples points uniformly by area on the mesh, from the random numbers
+ * u ([nsamples][3] float32 in [0, 1), caller-drawn): u0 picks the first
+ * triangle whose running (FP64) area sum exceeds u0 times the total, u1 and
+ * u2 give the barycentric weights (1 - sqrt(u1), sqrt(u1)(1 - u2),
+ * sqrt(u1) u2). face_weight ([nfaces] float32, may be NULL) multiplies the
+ * areas (0/1 restricts the draw to a set of faces, e.g. the largest
+ * component); if the weighted total is zero the samples come from the last
+ * triangle. Writes points [nsamples][3], face [nsamples] (triangle index),
+ * bary [nsamples][3], and, when normals is not NULL, the vertex normals
+ * (vnormals) interpolated with the same weights and normalised. */
+int psr_mesh_sample(psr_ctx* ctx, const float* verts, const float* vnormals, int64_t nverts, const int32_t* faces,
+                    int64_t nfaces, const float* face_weight, const float* u, int64_t nsamples, float* points,
+                    float* normals, int32_t* face, float* bary, void* workspace, size_t workspace_bytes,
+                    hipStream_t stream);
+
+/* dverts = dL/dverts ([nverts][3], overwritten) from dpoints = dL/dpoints of
+ * the samples: each sample adds its barycentric share to its triangle's
+ * three vertices (float atomics: the summation order, and so the last bits,
+ * may differ between runs). */
+int psr_mesh_sample_backward(psr_ctx* ctx, const int32_t* faces, int64_t nverts, const int32_t* face,
+                             const float* bary, const float* dpoints, int64_t nsamples, float* dverts,
+                             hipStream_t stream);
+
+/* Bytes of the Chamfer workspace for nx samples and ny target points (host only). */
+int psr_chamfer_workspace_bytes(int64_t nx, int64_t ny, size_t* bytes);
+
+/* Bidirectional L2 Chamfer distance (main Eq. 5) between x ([nx][3]) and y
+ * ([ny][3]): nn_x[i] / d_x[i] = nearest y and its squared distance, nn_y /
+ * d_y the same from y to x (brute force in FP32; equal distances go to the
+ * lower index), and, when loss is not NULL, *loss = mean(d_x) + mean(d_y)
+ * (one double, device memory, FP64 sums). */
+int psr_chamfer(psr_ctx* ctx, const float* x, int64_t nx, const float* y, int64_t ny, int32_t* nn_x, float* d_x,
+                int32_t* nn_y, float* d_y, double* loss, void* workspace, size_t workspace_bytes,
+                hipStream_t stream);
+
+/* grad_x = dL/dx of the Chamfer loss from its nearest-neighbour indices:
+ * 2 (x_i - y_nn_x[i]) / nx, plus 2 (x_i - y_j) / ny for every j with
+ * nn_y[j] = i (float atomics for the second term). */
+int psr_chamfer_backward(psr_ctx* ctx, const float* x, int64_t nx, const float* y, int64_t ny, const int32_t* nn_x,
+                         const int32_t* nn_y, float* grad_x, hipStream_t stream);
+
+/* Bytes of the components workspace (host only). */
+int psr_mesh_components_workspace_bytes(int64_t nverts, int64_t nfaces, size_t* bytes);
+
+/* Connected components of the mesh (triangles sharing a vertex): labels
+ * ([nverts] int32) = the smallest vertex index of each vertex's component;
+ * when largest ([nfaces] float32) is not NULL, 1 for the triangles of the
+ * component with the greatest area (ties: the lowest label), else 0.
+ * Synchronises `stream` after every relaxation pass (it reads a change flag);
+ * returns PSR_ENOTREADY if 256 passes did not settle the labels. */
+int psr_mesh_components(psr_ctx* ctx, const float* verts, int64_t nverts, const int32_t* faces, int64_t nfaces,
+                        int32_t* labels, float* largest, void* workspace, size_t workspace_bytes,
+                        hipStream_t stream);
 
 /* Test hook (host only): the case table the kernels use. ntri[256]: triangles
  * per sign pattern (bit k = corner k inside, corner k at offset (k&1,

@@ -26,6 +26,8 @@ PSR_EDEVICE = -4
 PSR_ENOTREADY = -5
 PSR_ENONFINITE = -6
 PSR_ETOOBIG = -7
+PSR_JOB_FORWARD = 0
+PSR_JOB_BACKWARD = 2
 
 
 class PSRError(RuntimeError):
@@ -48,6 +50,8 @@ class PsrJob(ctypes.Structure):
         ("dnormals", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
+        ("stages", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -82,6 +86,14 @@ def _declare(L):
         "psr_mc_counts": ([vp, vp, P(i64), P(i64), P(i32)], i32),
         "psr_marching_cubes_backward": ([vp, vp, i32, f32, vp, vp, vp, i64, vp, vp], i32),
         "psr_mc_case_table": ([vp, vp], i32),
+        "psr_mesh_sample_workspace_bytes": ([i64, P(sz)], i32),
+        "psr_mesh_sample": ([vp, vp, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, sz, vp], i32),
+        "psr_mesh_sample_backward": ([vp, vp, i64, vp, vp, vp, i64, vp, vp], i32),
+        "psr_chamfer_workspace_bytes": ([i64, i64, P(sz)], i32),
+        "psr_chamfer": ([vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp, sz, vp], i32),
+        "psr_chamfer_backward": ([vp, vp, i64, vp, i64, vp, vp, vp, vp], i32),
+        "psr_mesh_components_workspace_bytes": ([i64, i64, P(sz)], i32),
+        "psr_mesh_components": ([vp, vp, i64, vp, i64, vp, vp, vp, sz, vp], i32),
         "psr_ctx_stage_times": ([vp, P(f64), P(i64), i32], i32),
         "psr_ctx_reset_timers": ([vp], i32),
         "psr_stage_name": ([i32], ctypes.c_char_p),

@@ -12,6 +12,7 @@
 #include "psr.h"
 #include "psr_internal.h"
 #include "psr_mc.h"
+#include "psr_opt.h"
 
 namespace psr {
 
@@ -391,7 +392,10 @@ int psr_run_batched(psr_ctx* ctx, int njobs, const psr_job* jobs, hipStream_t st
   if (!ctx || njobs < 0 || (njobs > 0 && !jobs)) return PSR_EINVAL;
   for (int i = 0; i < njobs; ++i) {
     const psr_job& j = jobs[i];
-    if (!j.points || !j.normals || !j.chi || !j.saved || !j.workspace) return PSR_EINVAL;
+    if (j.stages != PSR_JOB_FORWARD && j.stages != PSR_JOB_BACKWARD) return PSR_EINVAL;
+    const bool bwd_only = j.stages == PSR_JOB_BACKWARD;
+    if ((!bwd_only && (!j.points || !j.normals)) || (bwd_only && !j.dchi)) return PSR_EINVAL;
+    if (!j.chi || !j.saved || !j.workspace) return PSR_EINVAL;
     if (!valid_res(j.res) || !valid_P(j.npoints) || !(j.sigma >= 0.0f) || !std::isfinite(j.sigma))
       return PSR_EINVAL;
     if (j.workspace_bytes < psr::ws_layout(j.res, j.npoints).total) return PSR_EINVAL;
@@ -410,7 +414,7 @@ int psr_run_batched(psr_ctx* ctx, int njobs, const psr_job* jobs, hipStream_t st
       const psr_job& j = jobs[i];
       if (j.res != res) continue;
       psr::JobArg a = make_job(j.points, j.normals, j.npoints, j.sigma, j.chi, j.saved, j.workspace);
-      fw.push_back(a);
+      if (j.stages == PSR_JOB_FORWARD) fw.push_back(a);
       if (j.dchi) {
         a.dchi = j.dchi;
         a.dpts = j.dpoints;
@@ -495,6 +499,78 @@ int psr_marching_cubes_backward(psr_ctx* ctx, const float* chi, int res, float i
                                nverts, dchi, stream)
              ? PSR_EDEVICE
              : PSR_OK;
+}
+
+int psr_mesh_sample_workspace_bytes(int64_t nfaces, size_t* bytes) {
+  if (!bytes || nfaces < 1) return PSR_EINVAL;
+  *bytes = psr::opt::sample_layout(nfaces).total;
+  return PSR_OK;
+}
+
+int psr_mesh_sample(psr_ctx* ctx, const float* verts, const float* vnormals, int64_t nverts, const int32_t* faces,
+                    int64_t nfaces, const float* face_weight, const float* u, int64_t nsamples, float* points,
+                    float* normals, int32_t* face, float* bary, void* workspace, size_t workspace_bytes,
+                    hipStream_t stream) {
+  if (!ctx || !verts || nverts < 1 || !faces || nfaces < 1 || nsamples < 0 || !workspace) return PSR_EINVAL;
+  if (nsamples > 0 && (!u || !points || !face || !bary || (normals && !vnormals))) return PSR_EINVAL;
+  if (workspace_bytes < psr::opt::sample_layout(nfaces).total || !aligned(workspace, 256)) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  return psr::opt::run_sample(verts, vnormals, faces, nfaces, face_weight, u, nsamples, points, normals, face, bary,
+                              workspace, stream)
+             ? PSR_EDEVICE
+             : PSR_OK;
+}
+
+int psr_mesh_sample_backward(psr_ctx* ctx, const int32_t* faces, int64_t nverts, const int32_t* face,
+                             const float* bary, const float* dpoints, int64_t nsamples, float* dverts,
+                             hipStream_t stream) {
+  if (!ctx || !faces || nverts < 1 || nsamples < 0 || !dverts) return PSR_EINVAL;
+  if (nsamples > 0 && (!face || !bary || !dpoints)) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  return psr::opt::run_sample_backward(faces, nverts, face, bary, dpoints, nsamples, dverts, stream) ? PSR_EDEVICE
+                                                                                                    : PSR_OK;
+}
+
+int psr_chamfer_workspace_bytes(int64_t nx, int64_t ny, size_t* bytes) {
+  if (!bytes || nx < 1 || ny < 1) return PSR_EINVAL;
+  *bytes = psr::opt::chamfer_ws(nx, ny);
+  return PSR_OK;
+}
+
+int psr_chamfer(psr_ctx* ctx, const float* x, int64_t nx, const float* y, int64_t ny, int32_t* nn_x, float* d_x,
+                int32_t* nn_y, float* d_y, double* loss, void* workspace, size_t workspace_bytes,
+                hipStream_t stream) {
+  if (!ctx || !x || !y || nx < 1 || ny < 1 || nx >= ((int64_t)1 << 31) || ny >= ((int64_t)1 << 31)) return PSR_EINVAL;
+  if (!nn_x || !d_x || !nn_y || !d_y || !workspace) return PSR_EINVAL;
+  if (workspace_bytes < psr::opt::chamfer_ws(nx, ny) || !aligned(workspace, 256)) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  return psr::opt::run_chamfer(x, nx, y, ny, nn_x, d_x, nn_y, d_y, loss, workspace, stream) ? PSR_EDEVICE : PSR_OK;
+}
+
+int psr_chamfer_backward(psr_ctx* ctx, const float* x, int64_t nx, const float* y, int64_t ny, const int32_t* nn_x,
+                         const int32_t* nn_y, float* grad_x, hipStream_t stream) {
+  if (!ctx || !x || !y || nx < 1 || ny < 1 || !nn_x || !nn_y || !grad_x) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  return psr::opt::run_chamfer_backward(x, nx, y, ny, nn_x, nn_y, grad_x, stream) ? PSR_EDEVICE : PSR_OK;
+}
+
+int psr_mesh_components_workspace_bytes(int64_t nverts, int64_t nfaces, size_t* bytes) {
+  if (!bytes || nverts < 1 || nfaces < 1) return PSR_EINVAL;
+  *bytes = psr::opt::comp_layout(nverts, nfaces).total;
+  return PSR_OK;
+}
+
+int psr_mesh_components(psr_ctx* ctx, const float* verts, int64_t nverts, const int32_t* faces, int64_t nfaces,
+                        int32_t* labels, float* largest, void* workspace, size_t workspace_bytes,
+                        hipStream_t stream) {
+  if (!ctx || !verts || nverts < 1 || nverts >= ((int64_t)1 << 31) || !faces || nfaces < 1 || !labels) return PSR_EINVAL;
+  if (!workspace || workspace_bytes < psr::opt::comp_layout(nverts, nfaces).total || !aligned(workspace, 256))
+    return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  // pointer jumping roughly doubles the reach of a label per pass (a mesh of
+  // the grids here settles in a few tens of passes); 256 passes at most
+  const int rc = psr::opt::run_components(verts, nverts, faces, nfaces, labels, largest, workspace, stream, 256);
+  return rc == 0 ? PSR_OK : (rc == -5 ? PSR_ENOTREADY : PSR_EDEVICE);
 }
 
 int psr_mc_case_table(int8_t* ntri, int8_t* edges) {

@@ -18,9 +18,15 @@ struct McHeader {
   int32_t pad;
 };
 
+constexpr int kMcThreads = 256;                 // threads per workgroup of the sweeps
+constexpr int kMcVpt = 4;                       // consecutive grid vertices (along j2) per thread
+constexpr int kMcBlock = kMcThreads * kMcVpt;   // grid vertices per workgroup
+constexpr int kMcGroup = 1024;                  // workgroup counts per first-level scan group
+
 struct McState {
   McHeader* hdr;
-  int2* blk;        // per 256-vertex workgroup: counts, then exclusive offsets (vertices, triangles)
+  int2* blk;        // per workgroup of the sweeps: counts, then offsets within its scan group (vertices, triangles)
+  int2* tops;       // per scan group: exclusive offsets
   uint32_t* vbase;  // per grid vertex with a crossing edge: first vertex index << 3 | crossing mask
 };
 
@@ -35,15 +41,19 @@ struct McOut {
 inline size_t mc_align(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct McLayout {
-  size_t hdr, blk, vbase, total;
+  size_t hdr, blk, tops, vbase, total;
 };
+
+inline size_t mc_blocks(int res) { return ((size_t)res * res * res + kMcBlock - 1) / kMcBlock; }
+inline size_t mc_groups(int res) { return (mc_blocks(res) + kMcGroup - 1) / kMcGroup; }
 
 inline McLayout state_layout(int res) {
   const size_t n = (size_t)res * res * res;
   McLayout L;
   L.hdr = 0;
   L.blk = mc_align(sizeof(McHeader));
-  L.vbase = L.blk + mc_align((n / 256) * sizeof(int2));
+  L.tops = L.blk + mc_align(mc_blocks(res) * sizeof(int2));
+  L.vbase = L.tops + mc_align(mc_groups(res) * sizeof(int2));
   L.total = L.vbase + mc_align(n * 4);
   return L;
 }
@@ -54,6 +64,7 @@ inline McState state_view(void* base, int res) {
   McState s;
   s.hdr = reinterpret_cast<McHeader*>(b + L.hdr);
   s.blk = reinterpret_cast<int2*>(b + L.blk);
+  s.tops = reinterpret_cast<int2*>(b + L.tops);
   s.vbase = reinterpret_cast<uint32_t*>(b + L.vbase);
   return s;
 }

@@ -5,8 +5,9 @@
 // Forward, over the r^3 grid vertices j (cells (j, j + 1) for j in
 // [0, r - 2]^3; vertex j owns the grid edges from j along +axis 0, 1, 2):
 //   count  per vertex: crossing edges it owns and triangles of its cell,
-//          summed per 256-vertex workgroup
-//   scan   exclusive offsets of the workgroup sums (one workgroup)
+//          summed per workgroup (1024 vertices: 4 consecutive ones along j2
+//          per thread, read as float4 rows)
+//   scan   exclusive offsets of the workgroup sums, in two levels
 //   emit   per vertex again: its mesh vertices (position by linear zero along
 //          the edge, normal from the central-difference gradient), the base
 //          index of its vertices, and its cell's triangles as global edge ids
@@ -29,57 +30,67 @@
 namespace psr {
 namespace mc {
 
-__device__ __forceinline__ float ld(const float* __restrict__ chi, int64_t i) { return chi[i]; }
-
 // central-difference gradient of the periodic grid at vertex (a, b, c), in domain units
 template <int R>
 __device__ __forceinline__ float3 grad_at(const float* __restrict__ chi, int a, int b, int c) {
   constexpr int M = R - 1;
-  auto at = [&](int x, int y, int z) { return ld(chi, ((int64_t)(x & M) * R + (y & M)) * R + (z & M)); };
+  auto at = [&](int x, int y, int z) { return chi[((int64_t)(x & M) * R + (y & M)) * R + (z & M)]; };
   const float h = 0.5f * (float)R;
   return make_float3((at(a + 1, b, c) - at(a - 1, b, c)) * h, (at(a, b + 1, c) - at(a, b - 1, c)) * h,
                      (at(a, b, c + 1) - at(a, b, c - 1)) * h);
 }
 
-struct Cell {
+// The kMcVpt vertices (j0, j1, j2 .. j2 + 3) of one thread: chi at the corners
+// of their cells, from four rows (j0 + o0, j1 + o1) loaded as float4 plus the
+// value one past the run.
+template <int R>
+struct Run {
   int j0, j1, j2;
-  int mask;  // bit a: the edge from j along axis a crosses the level
-  int cs;    // sign pattern of the cell at j (0 when the cell does not exist)
-  float c0;  // chi at j
-  float ce[3];  // chi at j + e_a
+  float v[2][2][kMcVpt + 1];  // [o0][o1][k]: chi(j0 + o0, j1 + o1, j2 + k)
+  bool ok0, ok1;              // rows j0 + 1 / j1 + 1 exist
+
+  __device__ __forceinline__ void load(const float* __restrict__ chi, int64_t e, float iso) {
+    constexpr int L = __builtin_ctz(R);
+    j2 = (int)(e & (R - 1));
+    j1 = (int)((e >> L) & (R - 1));
+    j0 = (int)(e >> (2 * L));
+    ok0 = j0 < R - 1;
+    ok1 = j1 < R - 1;
+    const bool ok2 = j2 + kMcVpt < R;
+#pragma unroll
+    for (int o0 = 0; o0 < 2; ++o0)
+#pragma unroll
+      for (int o1 = 0; o1 < 2; ++o1) {
+        const bool ok = (!o0 || ok0) && (!o1 || ok1);
+        const int64_t row = e + (int64_t)o0 * R * R + (int64_t)o1 * R;
+        const float4 q = ok ? *reinterpret_cast<const float4*>(chi + row) : make_float4(iso, iso, iso, iso);
+        v[o0][o1][0] = q.x;
+        v[o0][o1][1] = q.y;
+        v[o0][o1][2] = q.z;
+        v[o0][o1][3] = q.w;
+        v[o0][o1][4] = ok && ok2 ? chi[row + kMcVpt] : iso;
+      }
+  }
+  // crossing mask of the three edges owned by vertex j2 + k
+  __device__ __forceinline__ int mask(int k, float iso) const {
+    const bool in0 = v[0][0][k] < iso;
+    return (ok0 && (in0 != (v[1][0][k] < iso)) ? 1 : 0) | (ok1 && (in0 != (v[0][1][k] < iso)) ? 2 : 0) |
+           (j2 + k < R - 1 && (in0 != (v[0][0][k + 1] < iso)) ? 4 : 0);
+  }
+  // sign pattern of the cell at j2 + k (0 when the cell does not exist)
+  __device__ __forceinline__ int cell(int k, float iso) const {
+    if (!ok0 || !ok1 || j2 + k >= R - 1) return 0;
+    int cs = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) cs |= (v[c & 1][(c >> 1) & 1][k + (c >> 2)] < iso ? 1 : 0) << c;
+    return cs;
+  }
 };
 
-template <int R>
-__device__ __forceinline__ Cell classify(const float* __restrict__ chi, int64_t e, float iso) {
-  constexpr int L = __builtin_ctz(R);
-  Cell q;
-  q.j2 = (int)(e & (R - 1));
-  q.j1 = (int)((e >> L) & (R - 1));
-  q.j0 = (int)(e >> (2 * L));
-  const bool v0 = q.j0 < R - 1, v1 = q.j1 < R - 1, v2 = q.j2 < R - 1;
-  float c[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int o0 = k & 1, o1 = (k >> 1) & 1, o2 = k >> 2;
-    const bool ok = (!o0 || v0) && (!o1 || v1) && (!o2 || v2);
-    c[k] = ok ? ld(chi, e + (int64_t)o0 * R * R + o1 * R + o2) : iso;
-  }
-  q.c0 = c[0];
-  q.ce[0] = c[1];
-  q.ce[1] = c[2];
-  q.ce[2] = c[4];
-  const bool in0 = c[0] < iso;
-  q.mask = (v0 && (in0 != (c[1] < iso)) ? 1 : 0) | (v1 && (in0 != (c[2] < iso)) ? 2 : 0) |
-           (v2 && (in0 != (c[4] < iso)) ? 4 : 0);
-  int cs = 0;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) cs |= (c[k] < iso ? 1 : 0) << k;
-  q.cs = (v0 && v1 && v2) ? cs : 0;
-  return q;
-}
-
-// inclusive prefix over a 256-thread workgroup of two counters
+// inclusive prefix over a workgroup of NT threads of two counters; total too
+template <int NT>
 __device__ __forceinline__ int2 block_scan2(int2 v, int2* wtot, int2& total) {
+  constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -94,7 +105,7 @@ __device__ __forceinline__ int2 block_scan2(int2 v, int2* wtot, int2& total) {
   int2 base = make_int2(0, 0);
   total = make_int2(0, 0);
 #pragma unroll
-  for (int w = 0; w < 4; ++w) {
+  for (int w = 0; w < NW; ++w) {
     if (w < wid) {
       base.x += wtot[w].x;
       base.y += wtot[w].y;
@@ -106,119 +117,118 @@ __device__ __forceinline__ int2 block_scan2(int2 v, int2* wtot, int2& total) {
 }
 
 template <int R>
-__global__ __launch_bounds__(256) void k_mc_count(const float* __restrict__ chi, float iso, McState st) {
-  __shared__ int8_t ntri[256];
-  __shared__ int2 wtot[4];
-  ntri[threadIdx.x] = kTable.ntri[threadIdx.x];
-  __syncthreads();
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const Cell q = classify<R>(chi, e, iso);
+__global__ __launch_bounds__(kMcThreads) void k_mc_count(const float* __restrict__ chi, float iso, McState st) {
+  __shared__ int2 wtot[kMcThreads / 64];
+  const int64_t e = ((int64_t)blockIdx.x * kMcThreads + threadIdx.x) * kMcVpt;
+  int nv = 0, nt = 0;
+  if (e < (int64_t)R * R * R) {
+    Run<R> q;
+    q.load(chi, e, iso);
+#pragma unroll
+    for (int k = 0; k < kMcVpt; ++k) {
+      nv += __popc(q.mask(k, iso));
+      nt += kTable.ntri[q.cell(k, iso)];
+    }
+  }
   int2 tot;
-  block_scan2(make_int2(__popc(q.mask), ntri[q.cs]), wtot, tot);
+  block_scan2<kMcThreads>(make_int2(nv, nt), wtot, tot);
   if (threadIdx.x == 0) st.blk[blockIdx.x] = tot;
 }
 
-// Exclusive offsets of the per-workgroup counts, in place; the totals and
-// the grid size go to the header.
-__global__ __launch_bounds__(1024) void k_mc_scan(McState st, int nblocks, int res, float iso) {
-  __shared__ int2 wtot[16];
-  const int t = threadIdx.x, per = (nblocks + 1023) / 1024;
-  const int lo = t * per, hi = lo + per < nblocks ? lo + per : nblocks;
-  int2 s = make_int2(0, 0);
-  for (int i = lo; i < hi; ++i) {
-    s.x += st.blk[i].x;
-    s.y += st.blk[i].y;
+// first level: exclusive offsets of the workgroup counts within groups of
+// kMcGroup, and each group's total
+__global__ __launch_bounds__(kMcGroup) void k_mc_scan1(McState st, int nblocks) {
+  __shared__ int2 wtot[kMcGroup / 64];
+  const int i = blockIdx.x * kMcGroup + threadIdx.x;
+  const int2 c = i < nblocks ? st.blk[i] : make_int2(0, 0);
+  int2 tot;
+  const int2 incl = block_scan2<kMcGroup>(c, wtot, tot);
+  if (i < nblocks) st.blk[i] = make_int2(incl.x - c.x, incl.y - c.y);
+  if (threadIdx.x == 0) st.tops[blockIdx.x] = tot;
+}
+
+// second level: exclusive offsets of the groups (one workgroup); totals to the header
+__global__ __launch_bounds__(kMcGroup) void k_mc_scan2(McState st, int ngroups, int res, float iso) {
+  __shared__ int2 wtot[kMcGroup / 64];
+  int2 carry = make_int2(0, 0);
+  for (int g0 = 0; g0 < ngroups; g0 += kMcGroup) {
+    const int g = g0 + threadIdx.x;
+    const int2 c = g < ngroups ? st.tops[g] : make_int2(0, 0);
+    int2 tot;
+    const int2 incl = block_scan2<kMcGroup>(c, wtot, tot);
+    __syncthreads();  // wtot is reused by the next chunk
+    if (g < ngroups) st.tops[g] = make_int2(carry.x + incl.x - c.x, carry.y + incl.y - c.y);
+    carry.x += tot.x;
+    carry.y += tot.y;
   }
-  const int lane = t & 63, wid = t >> 6;
-  int2 v = s;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int x = __shfl_up(v.x, d, 64), y = __shfl_up(v.y, d, 64);
-    if (lane >= d) {
-      v.x += x;
-      v.y += y;
-    }
-  }
-  if (lane == 63) wtot[wid] = v;
-  __syncthreads();
-  int2 base = make_int2(0, 0), total = make_int2(0, 0);
-  for (int w = 0; w < 16; ++w) {
-    if (w < wid) {
-      base.x += wtot[w].x;
-      base.y += wtot[w].y;
-    }
-    total.x += wtot[w].x;
-    total.y += wtot[w].y;
-  }
-  int2 run = make_int2(base.x + v.x - s.x, base.y + v.y - s.y);  // exclusive start of this thread's chunk
-  for (int i = lo; i < hi; ++i) {
-    const int2 c = st.blk[i];
-    st.blk[i] = run;
-    run.x += c.x;
-    run.y += c.y;
-  }
-  if (t == 0) {
-    st.hdr->nv = total.x;
-    st.hdr->nt = total.y;
+  if (threadIdx.x == 0) {
+    st.hdr->nv = carry.x;
+    st.hdr->nt = carry.y;
     st.hdr->res = res;
     st.hdr->iso = iso;
-    st.hdr->status = total.x >= (1 << 29) ? -1 : 0;
+    st.hdr->status = carry.x >= (1 << 29) ? -1 : 0;
   }
 }
 
 template <int R>
-__global__ __launch_bounds__(256) void k_mc_emit(const float* __restrict__ chi, float iso, McState st, McOut out) {
-  __shared__ int8_t ntri[256];
-  __shared__ int8_t edges[256][kMaxTri * 3];
-  __shared__ int2 wtot[4];
-  ntri[threadIdx.x] = kTable.ntri[threadIdx.x];
-  for (int i = 0; i < kMaxTri * 3; ++i) edges[threadIdx.x][i] = kTable.edge[threadIdx.x][i];
-  __syncthreads();
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const Cell q = classify<R>(chi, e, iso);
-  const int nv = __popc(q.mask), nt = ntri[q.cs];
-  int2 tot;
-  const int2 incl = block_scan2(make_int2(nv, nt), wtot, tot);
-  const int2 b = st.blk[blockIdx.x];
-  const int vo = b.x + incl.x - nv, to = b.y + incl.y - nt;
-  if (q.mask) st.vbase[e] = ((uint32_t)vo << 3) | (uint32_t)q.mask;
-  const float inv_r = 1.0f / (float)R;
-  int v = vo;
+__global__ __launch_bounds__(kMcThreads) void k_mc_emit(const float* __restrict__ chi, float iso, McState st,
+                                                        McOut out) {
+  __shared__ int2 wtot[kMcThreads / 64];
+  const int64_t e = ((int64_t)blockIdx.x * kMcThreads + threadIdx.x) * kMcVpt;
+  const bool live = e < (int64_t)R * R * R;
+  Run<R> q;
+  int m[kMcVpt], cs[kMcVpt], nv = 0, nt = 0;
+  if (live) q.load(chi, e, iso);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (!((q.mask >> a) & 1)) continue;
-    if (v < out.vcap) {
-      const float t = (q.c0 - iso) / (q.c0 - q.ce[a]);
-      const float p0 = ((float)q.j0 + (a == 0 ? t : 0.0f)) * inv_r;
-      const float p1 = ((float)q.j1 + (a == 1 ? t : 0.0f)) * inv_r;
-      const float p2 = ((float)q.j2 + (a == 2 ? t : 0.0f)) * inv_r;
-      const float3 ga = grad_at<R>(chi, q.j0, q.j1, q.j2);
-      const float3 gb = grad_at<R>(chi, q.j0 + (a == 0), q.j1 + (a == 1), q.j2 + (a == 2));
-      float n0 = (1.0f - t) * ga.x + t * gb.x, n1 = (1.0f - t) * ga.y + t * gb.y, n2 = (1.0f - t) * ga.z + t * gb.z;
-      const float il = rsqrtf(n0 * n0 + n1 * n1 + n2 * n2);
-      n0 *= il;
-      n1 *= il;
-      n2 *= il;
-      out.verts[3 * (int64_t)v + 0] = p0;
-      out.verts[3 * (int64_t)v + 1] = p1;
-      out.verts[3 * (int64_t)v + 2] = p2;
-      out.normals[3 * (int64_t)v + 0] = n0;
-      out.normals[3 * (int64_t)v + 1] = n1;
-      out.normals[3 * (int64_t)v + 2] = n2;
-      if (out.edges) out.edges[v] = (int32_t)(3 * e + a);
-    }
-    ++v;
+  for (int k = 0; k < kMcVpt; ++k) {
+    m[k] = live ? q.mask(k, iso) : 0;
+    cs[k] = live ? q.cell(k, iso) : 0;
+    nv += __popc(m[k]);
+    nt += kTable.ntri[cs[k]];
   }
-  for (int i = 0; i < nt; ++i) {
-    const int64_t tri = (int64_t)to + i;
-    if (tri >= out.tcap) break;
+  int2 tot;
+  const int2 incl = block_scan2<kMcThreads>(make_int2(nv, nt), wtot, tot);
+  if (tot.x == 0 && tot.y == 0) return;  // no surface in this workgroup (uniform)
+  const int2 b = st.blk[blockIdx.x], g = st.tops[blockIdx.x / kMcGroup];
+  int v = g.x + b.x + incl.x - nv;
+  int64_t tri = (int64_t)g.y + b.y + incl.y - nt;
+  const float inv_r = 1.0f / (float)R;
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      const int le = edges[q.cs][3 * i + m];
-      const int a = edge_axis(le);
-      // owner of the edge: j plus the lower corner of local edge le
-      const int64_t owner = e + (int64_t)edge_lo(le, 0) * R * R + edge_lo(le, 1) * R + edge_lo(le, 2);
-      out.tris[3 * tri + m] = (int32_t)(3 * owner + a);
+  for (int k = 0; k < kMcVpt; ++k) {
+    const int64_t ek = e + k;
+    if (m[k]) st.vbase[ek] = ((uint32_t)v << 3) | (uint32_t)m[k];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (!((m[k] >> a) & 1)) continue;
+      if (v < out.vcap) {
+        const float c0 = q.v[0][0][k];
+        const float cb = a == 0 ? q.v[1][0][k] : (a == 1 ? q.v[0][1][k] : q.v[0][0][k + 1]);
+        const float t = (c0 - iso) / (c0 - cb);
+        const int j2 = q.j2 + k;
+        const float3 ga = grad_at<R>(chi, q.j0, q.j1, j2);
+        const float3 gb = grad_at<R>(chi, q.j0 + (a == 0), q.j1 + (a == 1), j2 + (a == 2));
+        float n0 = (1.0f - t) * ga.x + t * gb.x, n1 = (1.0f - t) * ga.y + t * gb.y, n2 = (1.0f - t) * ga.z + t * gb.z;
+        const float il = rsqrtf(n0 * n0 + n1 * n1 + n2 * n2);
+        out.verts[3 * (int64_t)v + 0] = ((float)q.j0 + (a == 0 ? t : 0.0f)) * inv_r;
+        out.verts[3 * (int64_t)v + 1] = ((float)q.j1 + (a == 1 ? t : 0.0f)) * inv_r;
+        out.verts[3 * (int64_t)v + 2] = ((float)j2 + (a == 2 ? t : 0.0f)) * inv_r;
+        out.normals[3 * (int64_t)v + 0] = n0 * il;
+        out.normals[3 * (int64_t)v + 1] = n1 * il;
+        out.normals[3 * (int64_t)v + 2] = n2 * il;
+        if (out.edges) out.edges[v] = (int32_t)(3 * ek + a);
+      }
+      ++v;
+    }
+    const int n = kTable.ntri[cs[k]];
+    for (int i = 0; i < n; ++i, ++tri) {
+      if (tri >= out.tcap) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int le = kTable.edge[cs[k]][3 * i + c];
+        // owner of the edge: this vertex plus the lower corner of local edge le
+        const int64_t owner = ek + (int64_t)edge_lo(le, 0) * R * R + edge_lo(le, 1) * R + edge_lo(le, 2);
+        out.tris[3 * tri + c] = (int32_t)(3 * owner + edge_axis(le));
+      }
     }
   }
 }
@@ -237,24 +247,46 @@ __global__ __launch_bounds__(256) void k_mc_link(McState st, McOut out) {
   }
 }
 
+// one thread per kMcVpt consecutive grid vertices; each sums, in a fixed
+// order, the contributions of the up to six crossing edges that meet there
 template <int R>
-__global__ __launch_bounds__(256) void k_mc_backward(const float* __restrict__ chi, float iso, McState st,
-                                                     const float* __restrict__ normals,
-                                                     const float* __restrict__ dverts, int64_t nverts,
-                                                     float* __restrict__ dchi) {
+__global__ __launch_bounds__(kMcThreads) void k_mc_backward(const float* __restrict__ chi, float iso, McState st,
+                                                            const float* __restrict__ normals,
+                                                            const float* __restrict__ dverts, int64_t nverts,
+                                                            float* __restrict__ dchi) {
   constexpr int L = __builtin_ctz(R);
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t e = ((int64_t)blockIdx.x * kMcThreads + threadIdx.x) * kMcVpt;
+  if (e >= (int64_t)R * R * R) return;
   if (st.hdr->res != R || st.hdr->iso != iso) {
     // the state comes from another grid size or level: no valid vertex map
-    dchi[e] = __int_as_float(0x7fc00000);
+    const float nan = __int_as_float(0x7fc00000);
+    *reinterpret_cast<float4*>(dchi + e) = make_float4(nan, nan, nan, nan);
     return;
   }
-  const int j[3] = {(int)(e >> (2 * L)), (int)((e >> L) & (R - 1)), (int)(e & (R - 1))};
-  const int64_t stride[3] = {(int64_t)R * R, R, 1};
-  const float cj = chi[e];
-  const bool inj = cj < iso;
-  float g = 0.0f;
-  // -(dL/dp . n) of the vertex on edge (owner, a), 0 beyond nverts
+  const int j2 = (int)(e & (R - 1)), j1 = (int)((e >> L) & (R - 1)), j0 = (int)(e >> (2 * L));
+  const int64_t s0 = (int64_t)R * R, s1 = R;
+  // chi along the run (j2 - 1 .. j2 + 4) and on the four neighbouring rows
+  float c[kMcVpt + 2], xm[kMcVpt], xp[kMcVpt], ym[kMcVpt], yp[kMcVpt];
+  {
+    const float4 q = *reinterpret_cast<const float4*>(chi + e);
+    c[1] = q.x;
+    c[2] = q.y;
+    c[3] = q.z;
+    c[4] = q.w;
+    c[0] = j2 > 0 ? chi[e - 1] : iso;
+    c[5] = j2 + kMcVpt < R ? chi[e + kMcVpt] : iso;
+    auto row = [&](bool ok, int64_t off, float* d) {
+      const float4 r = ok ? *reinterpret_cast<const float4*>(chi + e + off) : make_float4(iso, iso, iso, iso);
+      d[0] = r.x;
+      d[1] = r.y;
+      d[2] = r.z;
+      d[3] = r.w;
+    };
+    row(j0 > 0, -s0, xm);
+    row(j0 < R - 1, s0, xp);
+    row(j1 > 0, -s1, ym);
+    row(j1 < R - 1, s1, yp);
+  }
   auto gv = [&](int64_t owner, int a) {
     const uint32_t vb = st.vbase[owner];
     const int64_t v = (int64_t)(vb >> 3) + __popc(vb & 7u & ((1u << a) - 1u));
@@ -262,32 +294,39 @@ __global__ __launch_bounds__(256) void k_mc_backward(const float* __restrict__ c
     return -(dverts[3 * v] * normals[3 * v] + dverts[3 * v + 1] * normals[3 * v + 1] +
              dverts[3 * v + 2] * normals[3 * v + 2]);
   };
+  float out[kMcVpt];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    if (j[a] < R - 1) {  // the edge j -> j + e_a: this vertex is its lower end, weight 1 - t
-      const float cb = chi[e + stride[a]];
-      if (inj != (cb < iso)) {
-        const float t = (cj - iso) / (cj - cb);
-        g += (1.0f - t) * gv(e, a);
+  for (int k = 0; k < kMcVpt; ++k) {
+    const int64_t ek = e + k;
+    const float cj = c[k + 1];
+    const bool inj = cj < iso;
+    const int jj[3] = {j0, j1, j2 + k};
+    const float up[3] = {xp[k], yp[k], c[k + 2]}, dn[3] = {xm[k], ym[k], c[k]};
+    const int64_t stride[3] = {s0, s1, 1};
+    float g = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (jj[a] < R - 1 && inj != (up[a] < iso)) {  // edge j -> j + e_a: weight 1 - t
+        const float t = (cj - iso) / (cj - up[a]);
+        g += (1.0f - t) * gv(ek, a);
+      }
+      if (jj[a] > 0 && (dn[a] < iso) != inj) {  // edge j - e_a -> j: weight t
+        const float t = (dn[a] - iso) / (dn[a] - cj);
+        g += t * gv(ek - stride[a], a);
       }
     }
-    if (j[a] > 0) {  // the edge j - e_a -> j: this vertex is its upper end, weight t
-      const float ca = chi[e - stride[a]];
-      if ((ca < iso) != inj) {
-        const float t = (ca - iso) / (ca - cj);
-        g += t * gv(e - stride[a], a);
-      }
-    }
+    out[k] = g;
   }
-  dchi[e] = g;
+  *reinterpret_cast<float4*>(dchi + e) = make_float4(out[0], out[1], out[2], out[3]);
 }
 
 template <int R>
 static int forward_res(const float* chi, float iso, const McState& st, const McOut& out, hipStream_t s) {
-  const int nb = (int)((int64_t)R * R * R / 256);
-  hipLaunchKernelGGL(k_mc_count<R>, dim3(nb), dim3(256), 0, s, chi, iso, st);
-  hipLaunchKernelGGL(k_mc_scan, dim3(1), dim3(1024), 0, s, st, nb, R, iso);
-  hipLaunchKernelGGL(k_mc_emit<R>, dim3(nb), dim3(256), 0, s, chi, iso, st, out);
+  const int nb = (int)mc_blocks(R), ng = (int)mc_groups(R);
+  hipLaunchKernelGGL(k_mc_count<R>, dim3(nb), dim3(kMcThreads), 0, s, chi, iso, st);
+  hipLaunchKernelGGL(k_mc_scan1, dim3(ng), dim3(kMcGroup), 0, s, st, nb);
+  hipLaunchKernelGGL(k_mc_scan2, dim3(1), dim3(kMcGroup), 0, s, st, ng, R, iso);
+  hipLaunchKernelGGL(k_mc_emit<R>, dim3(nb), dim3(kMcThreads), 0, s, chi, iso, st, out);
   hipLaunchKernelGGL(k_mc_link, dim3(1024), dim3(256), 0, s, st, out);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
@@ -295,8 +334,9 @@ static int forward_res(const float* chi, float iso, const McState& st, const McO
 template <int R>
 static int backward_res(const float* chi, float iso, const McState& st, const float* normals, const float* dverts,
                         int64_t nverts, float* dchi, hipStream_t s) {
-  const int nb = (int)((int64_t)R * R * R / 256);
-  hipLaunchKernelGGL(k_mc_backward<R>, dim3(nb), dim3(256), 0, s, chi, iso, st, normals, dverts, nverts, dchi);
+  const int nb = (int)mc_blocks(R);
+  hipLaunchKernelGGL(k_mc_backward<R>, dim3(nb), dim3(kMcThreads), 0, s, chi, iso, st, normals, dverts, nverts,
+                     dchi);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

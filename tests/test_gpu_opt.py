@@ -1,0 +1,148 @@
+"""GPU parity of the optimisation loop's pieces (psr_mesh_sample and its
+backward, psr_chamfer and its backward, psr_mesh_components) against the
+FP64 oracle (oracle/opt.py), and the loop itself (main Sec. 3.2).
+
+Both sides read the same float32 inputs (the oracle's Marching Cubes mesh of
+an analytic field rounded once to float32, the same random numbers, the same
+clouds). Integer results (triangle picked, component labels, the largest
+component) must agree exactly; positions, distances and gradients within
+1e-5 relative. A nearest neighbour is an integer decided by FP32 distances on
+the GPU: where the two sides pick different neighbours, both must be at the
+same (minimal) distance within that tolerance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import psr_synth as S
+from gpu_common import announce, host, l2_rel, require_gpu, to_dev, torch
+from oracle import mc as omc
+from oracle import opt as oopt
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return require_gpu()
+
+
+def _mesh32(kind="sphere", r=48):
+    x = np.indices((r, r, r)).transpose(1, 2, 3, 0) / r
+    if kind == "sphere":
+        f = np.linalg.norm(x - 0.5, axis=-1) - 0.3
+    else:  # two spheres
+        f = np.minimum(np.linalg.norm(x - [0.3, 0.5, 0.5], axis=-1) - 0.15,
+                       np.linalg.norm(x - [0.72, 0.5, 0.5], axis=-1) - 0.1)
+    m = omc.marching_cubes(f.astype(np.float32).astype(np.float64))
+    return (m["verts"].astype(np.float32), m["faces"].astype(np.int32), m["normals"].astype(np.float32))
+
+
+def test_sampling_matches_oracle(dev):
+    from paper_2106_03452_amd import optimize as O
+    announce("mesh sampling vs oracle")
+    v, f, vn = _mesh32("two")
+    u = np.random.default_rng(0).random((20000, 3)).astype(np.float32)
+    w = (np.arange(len(f)) % 3 != 0).astype(np.float32)  # a subset of the faces
+    for weight in (None, w):
+        pts, nrm, face, bary = O.sample_raw(to_dev(v, dev), torch.from_numpy(f).to(dev), to_dev(u, dev),
+                                            to_dev(vn, dev), to_dev(weight, dev) if weight is not None else None)
+        ref = oopt.sample_mesh(v, f, u, vn, weight)
+        same = host(face) == ref["face"]
+        print(f"sampling: {same.mean() * 100:.4f}% same triangle")
+        assert same.all()
+        assert np.abs(host(pts) - ref["points"]).max() <= 1e-6
+        assert np.abs(host(nrm) - ref["normals"]).max() <= 1e-5
+        assert np.abs(host(bary) - ref["bary"]).max() <= 1e-6
+
+
+def test_sampling_backward_matches_oracle(dev):
+    from paper_2106_03452_amd import optimize as O
+    announce("mesh sampling backward vs oracle")
+    v, f, _ = _mesh32()
+    u = np.random.default_rng(1).random((30000, 3)).astype(np.float32)
+    dp = np.random.default_rng(2).standard_normal((30000, 3)).astype(np.float32)
+    V = to_dev(v, dev).requires_grad_(True)
+    x = O.SampleFunction.apply(V, torch.from_numpy(f).to(dev), to_dev(u, dev))
+    (x * to_dev(dp, dev)).sum().backward()
+    ref = oopt.sample_mesh(v, f, u)
+    g = oopt.sample_mesh_backward(f, ref, dp, len(v))
+    e = l2_rel(host(V.grad), g)
+    print(f"sampling backward e={e:.2e}")
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("nx,ny", [(20000, 20000), (5000, 30000), (257, 1)])
+def test_chamfer_matches_oracle(dev, nx, ny):
+    from paper_2106_03452_amd import optimize as O
+    announce(f"chamfer {nx} x {ny} vs oracle")
+    rng = np.random.default_rng(nx + ny)
+    x = rng.random((nx, 3)).astype(np.float32)
+    y = rng.random((ny, 3)).astype(np.float32)
+    loss, nnx, dx, nny, dy = O.chamfer_raw(to_dev(x, dev), to_dev(y, dev))
+    ref = oopt.chamfer(x, y)
+    for d_g, d_r, nn_g, a, b in ((host(dx), ref["d_x"], host(nnx).astype(np.int64), x, y),
+                                 (host(dy), ref["d_y"], host(nny).astype(np.int64), y, x)):
+        assert np.abs(d_g - d_r).max() <= 1e-5 * max(d_r.max(), 1e-12)
+        # a different neighbour only on a tie at the tolerance
+        dd = ((a.astype(np.float64) - b.astype(np.float64)[nn_g]) ** 2).sum(1)
+        assert np.abs(dd - d_r).max() <= 1e-5 * max(d_r.max(), 1e-12)
+    assert abs(float(loss) - ref["loss"]) <= 1e-6 * ref["loss"]
+    X = to_dev(x, dev).requires_grad_(True)
+    O.ChamferFunction.apply(X, to_dev(y, dev)).backward()
+    e = l2_rel(host(X.grad), ref["grad"])
+    print(f"chamfer {nx}x{ny}: loss {float(loss):.6e} (ref {ref['loss']:.6e}), grad e={e:.2e}")
+    assert e <= 1e-5
+
+
+def test_components_match_oracle(dev):
+    from paper_2106_03452_amd import optimize as O
+    announce("mesh components vs oracle")
+    v, f, _ = _mesh32("two", 64)
+    lab, w = O.components(to_dev(v, dev), torch.from_numpy(f).to(dev))
+    ref = oopt.components(f, len(v))
+    assert np.array_equal(host(lab).astype(np.int64), ref)
+    assert np.array_equal(host(w), oopt.largest_component_faces(v, f))
+
+
+def test_one_step_gradient_matches_oracle_chain(dev):
+    """main Eq. 5 end to end: the Chamfer loss of area samples of the mesh of
+    the solved grid, back to the points and normals (Eq. 6 through the mesh),
+    against the oracle's chain on the same inputs and random numbers."""
+    from paper_2106_03452_amd import function as F
+    from paper_2106_03452_amd import mesh as M
+    from paper_2106_03452_amd import optimize as O
+    announce("optimisation step gradient vs oracle chain, 32^3")
+    res, sigma = 32, 2.0
+    rng = np.random.default_rng(5)
+    sh = S.tiny_case(7, res, 2000, kind="sphere")
+    target = S.tiny_case(11, res, 3000, kind="torus").points
+    u = rng.random((3000, 3)).astype(np.float32)
+    chi_r, aux = oracle.forward(sh.points, sh.normals, res, sigma)
+    assert np.abs(chi_r).min() > 1e-4  # both sides' grids give the same mesh
+    pts = to_dev(sh.points, dev).requires_grad_(True)
+    nrm = to_dev(sh.normals, dev).requires_grad_(True)
+    loss, _ = O.step_loss(pts, nrm, to_dev(target, dev), res, sigma, to_dev(u, dev))
+    loss.backward()
+    m = omc.marching_cubes(chi_r)
+    s = oopt.sample_mesh(m["verts"], m["faces"], u)
+    c = oopt.chamfer(s["points"], target)
+    dv = oopt.sample_mesh_backward(m["faces"], s, c["grad"], len(m["verts"]))
+    G = omc.mc_backward(m, dv, res)
+    dc, dn = oracle.backward(aux, G)
+    e_l = abs(float(loss) - c["loss"]) / c["loss"]
+    e_c, e_n = l2_rel(host(pts.grad), dc), l2_rel(host(nrm.grad), dn)
+    print(f"step: loss {float(loss):.6e} (ref {c['loss']:.6e}) e_dpoints={e_c:.2e} e_dnormals={e_n:.2e}")
+    assert e_l <= 1e-5 and e_c <= 1e-4 and e_n <= 1e-4
+
+
+def test_short_optimisation_lowers_chamfer(dev):
+    from paper_2106_03452_amd import optimize as O
+    announce("short coarse-to-fine optimisation")
+    target = to_dev(S.tiny_case(8, 64, 5000, kind="torus").points, dev)
+    sched = [O.Level(32, 2.0, 150), O.Level(64, 2.0, 100)]
+    r = O.optimise(target, sched, npoints=5000, resample_every=100, log_every=25, seed=1)
+    first, last = r.history[0][3], r.history[-1][3]
+    print(f"Chamfer {first:.3e} -> {last:.3e}; ms/iter {r.ms_per_iter}")
+    assert last < 0.3 * first
+    assert torch.isfinite(r.points).all() and r.faces.shape[0] > 0
