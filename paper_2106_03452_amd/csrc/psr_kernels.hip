@@ -767,10 +767,6 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
   __shared__ __align__(16) cf rows[TR * LS];
   __shared__ cf stw[M];      // FFT table of length M
   __shared__ cf rtw[M + 1];  // W_RES^k, k in [0, M], for the r2c post-processing
-  if constexpr (MODE != MODE_VOUT) {
-    stage_table<BR>(stw, tw + M, M);
-    stage_table<BR>(rtw, tw + RES, M + 1);
-  }
   float* rf = reinterpret_cast<float*>(rows);
   constexpr int NC = MODE == MODE_BWDH || MODE == MODE_BWDA ? 1 : 3;  // channels in the grid
   int T, c;
@@ -781,14 +777,23 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
   Ranges R{};
   if constexpr (MODE != MODE_LOADV) R = tile_ranges<RES>(off, j0, tb);
   const int total = R.total;
+  // the row tile of workgroup 0 records the backward scalars for the final pass
+  const bool records = T == 0;
+  // workgroups with nothing to do leave before staging any table (most row
+  // tiles of a large grid hold no point); the test is uniform per workgroup
   if constexpr (MODE == MODE_SPLAT) {
     // no point touches this row tile (of a plane some point may reach): its
     // rows and their spectra are zero; P2 takes them as zero without reading
     if (total == 0) return;
   }
+  if constexpr (MODE == MODE_BWDH) {
+    if (total == 0 && !records) return;  // done by MODE_BWDA
+  }
+  if constexpr (MODE != MODE_VOUT) {
+    stage_table<BR>(stw, tw + M, M);
+    stage_table<BR>(rtw, tw + RES, M + 1);
+  }
 
-  // the row tile of workgroup 0 records the backward scalars for the final pass
-  const bool records = T == 0;
   if constexpr (MODE == MODE_BWDA) {
     // rows of tiles that W reaches wait for the reductions (MODE_BWDH)
     const bool later = total > 0 || records;
@@ -796,10 +801,7 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
     if (later) return;
   } else {
     float3 sqa = make_float3(1.0f, 0.0f, 1.0f);
-    if constexpr (MODE == MODE_BWDH) {
-      if (total == 0 && !records) return;  // done by MODE_BWDA
-      sqa = bwd_scalars<BR>(bpart, RES * NT, hdr, bs, records);
-    }
+    if constexpr (MODE == MODE_BWDH) sqa = bwd_scalars<BR>(bpart, RES * NT, hdr, bs, records);
     fill_rows<RES, TR, BR, MODE == MODE_VOUT ? MODE_SPLAT : MODE>(rows, sorted, R, gin, sqa, j0, a0, c);
   }
 
@@ -986,7 +988,9 @@ __device__ __forceinline__ float spectral_F(const float* g1, int k0, float g12, 
   const float q0 = kappa_of(k0, RES);
   const float K2 = q0 * q0 + q12;
   constexpr float c = -1.0f / (6.283185307179586f * (float)RES * (float)RES * (float)RES);
-  return K2 == 0.0f ? 0.0f : g1[k0] * g12 * c / K2;
+  // the hardware reciprocal (1 ulp) instead of a full-precision division:
+  // it is per element of the j0 passes, where VALU time is half the kernel
+  return K2 == 0.0f ? 0.0f : (g1[k0] * g12 * c) * __builtin_amdgcn_rcpf(K2);
 }
 
 template <int RES, bool IN_C, bool SKIP>
@@ -1204,8 +1208,6 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
   __shared__ __align__(16) cf rows[TR * LS];
   __shared__ cf stw[M];      // FFT table of length M
   __shared__ cf rtw[M + 1];  // W_RES^k, k in [0, M], for the c2r pre-processing
-  stage_table<BR>(stw, tw + M, M);
-  stage_table<BR>(rtw, tw + RES, M + 1);
   const float* rf = reinterpret_cast<const float*>(rows);
   constexpr int NC = MODE == MODE_BWD ? 3 : 1;  // channels in the grid
   int T, c;
@@ -1218,9 +1220,12 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
   const int total = R.total;
   if constexpr (MODE != MODE_DBG) {
     // the backward pass only produces per-point partials: a tile that no
-    // point touches has nothing to do (uniform across the workgroup)
+    // point touches has nothing to do (uniform across the workgroup; before
+    // any table is staged)
     if (MODE == MODE_BWD && total == 0) return;
   }
+  stage_table<BR>(stw, tw + M, M);
+  stage_table<BR>(rtw, tw + RES, M + 1);
   // the thread's point records are fetched now, under the grid loads
   constexpr int KR = 4;
   Recs<KR> recs;
