@@ -718,6 +718,11 @@ def main():
         s3 = make_step(b3, ctx)
         d3 = timed(s3, args.steps, args.warmup, torch)
         ms3 = d3 / args.steps * 1e3
+        ctx.set("timers", 1)
+        ctx.reset_timers()
+        timed(s3, max(5, args.steps // 3), 1, torch)
+        st3 = {k: round(v[0] / v[1], 4) for k, v in ctx.stage_times().items() if v[1] > 0}
+        ctx.set("timers", 0)
         fp3, ft3 = live_fractions(sh3.points, 256)
         sk3 = skip_aware_bytes(256, sh3.P, fp3, ft3)
         secondary["fwd_bwd_256_no_skip"] = {
@@ -726,7 +731,8 @@ def main():
             "solves_per_s": round(args.steps / d3, 2), "ms": round(ms3, 4),
             "live_plane_fraction": round(fp3, 4), "live_tile_fraction": round(ft3, 4),
             "algorithmic_bytes": round(sk3), "hbm_frac": round(rate(sk3, ms3) / HBM_PEAK_GBS, 4),
-            "dense_equivalent_frac": round(rate(b_stage(256, sh3.P), ms3) / HBM_PEAK_GBS, 4)}
+            "dense_equivalent_frac": round(rate(b_stage(256, sh3.P), ms3) / HBM_PEAK_GBS, 4),
+            "stage_ms": dict(sorted(st3.items(), key=lambda kv: -kv[1]))}
         del b3
         sh1 = S.config_c1()
         b1 = prepare(sh1, dev, torch, F)
