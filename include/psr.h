@@ -219,6 +219,58 @@ int psr_debug_splat(psr_ctx* ctx, const float* points, const float* normals, int
                     hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Slab-decomposed forward solve for large grids (16^3 to 1024^3): the
+ * large-scene form of the solver (main Sec. 5: the dense grid's memory grows
+ * with the cube of the resolution). It computes the same chi as psr_forward
+ * (main Eqs. 2-4, same conventions and options) with the grid cut along j0
+ * into `slabs` slabs of res/slabs planes. Each stage runs per slab (splat +
+ * r2c along j2, FFT along j1; inverse FFT along k1, c2r along k2, gather at
+ * the slab's points) or per pencil owner (FFT along j0 with the spectral
+ * operator of main Eq. 3 over res/slabs values of k1), and the spectrum
+ * moves between them in equal blocks, as an all-to-all between processes
+ * would move it; the gather reads one halo plane of the next slab. Forward
+ * only: there is no backward of this call.
+ * The result does not depend on `slabs`: chi and the scalars are the same
+ * bit for bit for every slab count.
+ * ------------------------------------------------------------------------ */
+#define PSR_SLAB_MAX_RES 1024
+#define PSR_SLAB_MAX_SLABS 64
+
+/* Scalars of the slab forward (main Eq. 4), written to device memory. */
+typedef struct psr_slab_result {
+  double mu;       /* mean of chi' at the points (FP64) */
+  double cscale;   /* c: chi'(0,0,0) - mu (reading B) or chi'(0,0,0) (reading A) */
+  double scale;    /* m / |c|; NaN when status != PSR_OK */
+  double chi0;     /* chi'(0,0,0) */
+  int32_t status;  /* PSR_OK, PSR_EDEGENERATE or PSR_ENONFINITE */
+  int32_t flags;   /* bit 0: a non-finite coordinate or normal was seen */
+} psr_slab_result;
+
+/* Workspace bytes of the slab forward (host only). res: power of two in
+ * [16, 1024]; slabs: power of two in [1, min(64, res)]; npoints may be 0 for
+ * psr_slab_debug_spectral. About 48 res^2 (res/2 + 16) bytes of grid buffers
+ * plus 80 bytes per point (26 GB at 1024^3). */
+int psr_slab_workspace_bytes(int res, int64_t npoints, int slabs, size_t* bytes);
+
+/* Slab forward. points, normals [npoints][3] float32; chi [res][res][res]
+ * float32 output (written in full; slab g is planes [g res/slabs,
+ * (g+1) res/slabs)); result: one psr_slab_result in device memory, written
+ * by the last kernel (read it after synchronising the stream); workspace at
+ * least psr_slab_workspace_bytes bytes, 256-byte aligned. Data-dependent
+ * errors go to result->status (the grid is then NaN). Stream-ordered and
+ * asynchronous; returns PSR_EINVAL for a bad argument (nothing launched) or
+ * PSR_EDEVICE if a launch failed. */
+int psr_slab_forward(psr_ctx* ctx, const float* points, const float* normals, int64_t npoints, int res, float sigma,
+                     int slabs, float* chi, psr_slab_result* result, void* workspace, size_t workspace_bytes,
+                     hipStream_t stream);
+
+/* Test hook: the slab passes on a given field v ([3][res^3] float32) instead
+ * of the splat; writes the unnormalised chi' ([res^3]) as psr_debug_spectral
+ * does. workspace: psr_slab_workspace_bytes(res, 0, slabs) bytes. */
+int psr_slab_debug_spectral(psr_ctx* ctx, const float* field, int res, float sigma, int slabs, float* chi_prime,
+                            void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Marching Cubes on the indicator grid and its inverse-normal gradient
  * (main Sec. 3.2: the mesh of chi by Marching Cubes, Lorensen and Cline 1987;
  * main Eq. 6: dp_mesh/dchi = -n_mesh).

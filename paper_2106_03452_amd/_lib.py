@@ -81,6 +81,9 @@ def _declare(L):
         "psr_run_batched": ([vp, i32, P(PsrJob), vp], i32),
         "psr_debug_spectral": ([vp, vp, i32, f32, vp, vp, sz, vp], i32),
         "psr_debug_splat": ([vp, vp, vp, i64, i32, vp, vp, vp, sz, vp], i32),
+        "psr_slab_workspace_bytes": ([i32, i64, i32, P(sz)], i32),
+        "psr_slab_forward": ([vp, vp, vp, i64, i32, f32, i32, vp, vp, vp, sz, vp], i32),
+        "psr_slab_debug_spectral": ([vp, vp, i32, f32, i32, vp, vp, sz, vp], i32),
         "psr_mc_state_bytes": ([i32, P(sz)], i32),
         "psr_marching_cubes": ([vp, vp, i32, f32, vp, vp, vp, i64, vp, i64, vp, vp], i32),
         "psr_mc_counts": ([vp, vp, P(i64), P(i64), P(i32)], i32),

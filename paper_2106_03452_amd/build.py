@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpsr.so")
-SOURCES = ["psr_kernels.hip", "psr_mc.hip", "psr_opt.hip", "psr_api.cpp"]
+SOURCES = ["psr_kernels.hip", "psr_mc.hip", "psr_opt.hip", "psr_slab.hip", "psr_api.cpp"]
 ARCH = os.environ.get("PSR_OFFLOAD_ARCH", "gfx950")
 
 

@@ -208,6 +208,10 @@ __device__ __forceinline__ void fft(cf* reg, cf* line, int lt, const cf* __restr
     stage<512, 8, 1, DIR, IN_REG, false>(reg, line, lt, tw, swz);
     stage<512, 8, 8, DIR, false, false>(reg, line, lt, tw, swz);
     stage<512, 8, 64, DIR, false, OUT_REG>(reg, line, lt, tw, swz);
+  } else if constexpr (L == 1024) {
+    stage<1024, 16, 1, DIR, IN_REG, false>(reg, line, lt, tw, swz);
+    stage<1024, 16, 16, DIR, false, false>(reg, line, lt, tw, swz);
+    stage<1024, 4, 256, DIR, false, OUT_REG>(reg, line, lt, tw, swz);
   }
 }
 

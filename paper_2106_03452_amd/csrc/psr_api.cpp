@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -13,6 +14,7 @@
 #include "psr_internal.h"
 #include "psr_mc.h"
 #include "psr_opt.h"
+#include "psr_slab.h"
 
 namespace psr {
 
@@ -141,6 +143,43 @@ psr::JobArg make_job(const float* pts, const float* nrm, int64_t P, float sigma,
   return j;
 }
 
+bool valid_slab(int res, int slabs) {
+  return res >= psr::kSlabMinRes && res <= psr::kSlabMaxRes && (res & (res - 1)) == 0 && slabs >= 1 &&
+         slabs <= psr::kMaxSlabs && slabs <= res && (slabs & (slabs - 1)) == 0;
+}
+
+static_assert(sizeof(psr_slab_result) == sizeof(psr::SlabResult) &&
+                  offsetof(psr_slab_result, chi0) == offsetof(psr::SlabResult, chi0) &&
+                  offsetof(psr_slab_result, status) == offsetof(psr::SlabResult, status),
+              "psr_slab_result and the kernels' SlabResult share one layout");
+
+psr::SlabArgs slab_args(psr_ctx* ctx, const psr::SlabLayout& L, void* ws, int64_t P, float sigma, int slabs,
+                        float* chi) {
+  char* b = static_cast<char*>(ws);
+  psr::SlabArgs a{};
+  a.tw = ctx->tw;
+  a.chi = chi;
+  a.hdr = reinterpret_cast<psr::SlabHeader*>(b + L.hdr);
+  a.counts = reinterpret_cast<int*>(b + L.counts);
+  a.off = reinterpret_cast<int*>(b + L.off);
+  a.bsum = reinterpret_cast<int*>(b + L.bsum);
+  a.tmp = reinterpret_cast<psr::PointRec*>(b + L.tmp);
+  a.colrank = reinterpret_cast<int2*>(b + L.colrank);
+  a.sorted = reinterpret_cast<psr::PointRec*>(b + L.sorted);
+  a.val = reinterpret_cast<double*>(b + L.val);
+  a.red = reinterpret_cast<double*>(b + L.red);
+  a.A = reinterpret_cast<psr::cf*>(b + L.A);
+  a.X = reinterpret_cast<psr::cf*>(b + L.X);
+  a.Z = reinterpret_cast<psr::cf*>(b + L.Z);
+  a.halo = reinterpret_cast<float*>(b + L.halo);
+  a.P = P;
+  a.sigma = sigma;
+  a.m = (float)ctx->m;
+  a.reading = ctx->reading;
+  a.G = slabs;
+  return a;
+}
+
 psr::Exec make_exec(psr_ctx* ctx, hipStream_t stream) {
   psr::Exec x;
   x.stream = stream;
@@ -186,7 +225,9 @@ const char* const kStageNames[psr::NUM_STAGES] = {
     "bin", "P1_splat_r2c", "P2_fft_j1", "P3_fft_j0_spectral_ifft_j0", "P4_ifft_j1", "P5_c2r_gather",
     "fwd_reduce", "normalize", "bwd_reduce", "B1_cotangent_r2c", "B2_fft_j1", "B3_fft_j0_conjop_ifft_j0",
     "B4_ifft_j1", "B5_c2r_gather", "bwd_finalize", "P12_splat_r2c_fft_j1", "P45_ifft_j1_c2r_gather",
-    "B12_cotangent_r2c_fft_j1", "B45_ifft_j1_c2r_gather", "B1a_reduce_r2c"};
+    "B12_cotangent_r2c_fft_j1", "B45_ifft_j1_c2r_gather", "B1a_reduce_r2c", "slab_bin", "S1_splat_r2c",
+    "S2_fft_j1_exchange", "S3_pencil_fft_j0_spectral", "S4_ifft_k1", "S5_c2r_halo", "slab_gather_mean",
+    "slab_normalize"};
 
 }  // namespace
 
@@ -357,6 +398,43 @@ int psr_backward(psr_ctx* ctx, int64_t npoints, int res, float sigma, const floa
   j.dpts = dpoints;
   j.dnrm = dnormals;
   return psr::run_jobs(x, res, &j, 1, psr::RUN_BACKWARD);
+}
+
+int psr_slab_workspace_bytes(int res, int64_t npoints, int slabs, size_t* bytes) {
+  if (!bytes || !valid_slab(res, slabs) || npoints < 0 || npoints > ((int64_t)1 << 30)) return PSR_EINVAL;
+  *bytes = psr::slab_layout(res, npoints, slabs).total;
+  return PSR_OK;
+}
+
+int psr_slab_forward(psr_ctx* ctx, const float* points, const float* normals, int64_t npoints, int res, float sigma,
+                     int slabs, float* chi, psr_slab_result* result, void* workspace, size_t workspace_bytes,
+                     hipStream_t stream) {
+  if (!ctx || !points || !normals || !chi || !result || !workspace) return PSR_EINVAL;
+  if (!valid_slab(res, slabs) || !valid_P(npoints) || !(sigma >= 0.0f) || !std::isfinite(sigma)) return PSR_EINVAL;
+  if (!aligned(workspace, 256) || !aligned(chi, 16) || !aligned(result, 8)) return PSR_EINVAL;
+  const psr::SlabLayout L = psr::slab_layout(res, npoints, slabs);
+  if (workspace_bytes < L.total) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  psr::Exec x = make_exec(ctx, stream);
+  psr::SlabArgs a = slab_args(ctx, L, workspace, npoints, sigma, slabs, chi);
+  a.pts = points;
+  a.nrm = normals;
+  a.result = reinterpret_cast<psr::SlabResult*>(result);
+  return psr::run_slab(x, res, a) ? PSR_EDEVICE : PSR_OK;
+}
+
+int psr_slab_debug_spectral(psr_ctx* ctx, const float* field, int res, float sigma, int slabs, float* chi_prime,
+                            void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!ctx || !field || !chi_prime || !workspace) return PSR_EINVAL;
+  if (!valid_slab(res, slabs) || !(sigma >= 0.0f) || !std::isfinite(sigma)) return PSR_EINVAL;
+  if (!aligned(workspace, 256) || !aligned(chi_prime, 16) || !aligned(field, 16)) return PSR_EINVAL;
+  const psr::SlabLayout L = psr::slab_layout(res, 0, slabs);
+  if (workspace_bytes < L.total) return PSR_EINVAL;
+  DeviceGuard g(ctx->device);
+  psr::Exec x = make_exec(ctx, stream);
+  psr::SlabArgs a = slab_args(ctx, L, workspace, 0, sigma, slabs, chi_prime);
+  a.field = field;
+  return psr::run_slab(x, res, a) ? PSR_EDEVICE : PSR_OK;
 }
 
 int psr_ctx_prepare(psr_ctx* ctx, int res, float sigma, hipStream_t stream) {

@@ -66,6 +66,14 @@ enum Stage {
   STAGE_B12,  // plane pass: B1 + B2
   STAGE_B45,  // plane pass: B4 + B5
   STAGE_B1A,  // two-pass path: backward reductions + r2c of point-free row tiles
+  STAGE_SLAB_BIN,     // slab solve: binning by floor plane and row
+  STAGE_S1,           // slab solve: splat + r2c along j2, per slab
+  STAGE_S2,           // slab solve: FFT along j1, per slab, into the exchange blocks
+  STAGE_S3,           // slab solve: j0 pencils, spectral operator, per owner
+  STAGE_S4,           // slab solve: inverse FFT along k1, per slab
+  STAGE_S5,           // slab solve: c2r along k2 + halo plane, per slab
+  STAGE_SLAB_GATHER,  // slab solve: gather at the points + FP64 mean
+  STAGE_SLAB_NORM,    // slab solve: normalisation, per slab
   NUM_STAGES
 };
 

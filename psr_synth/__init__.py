@@ -291,6 +291,39 @@ def config_c5(seed: int = 4, n_requests: int = 2000, workers: int = 1):
     return list(zip(shapes, bwds)), arrivals_unit
 
 
+def config_scene(seed: int = 5, P: int = 1_000_000, res: int = 1024, n_objects: int = 16,
+                 table=(512, 1024)) -> Shape:
+    """Large-scene stand-in for the slab solve (1024^3, sigma 2): n_objects
+    spheres, rotated tori and superellipsoids of size 0.04 to 0.12 at uniform
+    places in [0.12, 0.88]^3, points shared in proportion to size squared (a
+    proxy for area), positions jittered by N(0, (0.25 / res)^2)."""
+    rng = rng_for(seed)
+    size = rng.uniform(0.04, 0.12, n_objects)
+    share = size ** 2 / (size ** 2).sum()
+    counts = np.floor(share * P).astype(np.int64)
+    counts[: P - counts.sum()] += 1
+    ps, ns = [], []
+    for k in range(n_objects):
+        kind = int(rng.integers(0, 3))
+        c = rng.uniform(0.12, 0.88, 3)
+        if kind == 0:
+            p, n = sphere(rng, int(counts[k]), c, size[k])
+        elif kind == 1:
+            p, n = torus(rng, int(counts[k]), c, size[k], size[k] * rng.uniform(0.25, 0.45), random_rotation(rng))
+        else:
+            axes = size[k] * rng.uniform(0.5, 1.0, 3)
+            e1, e2 = rng.uniform(0.3, 2.0, 2)
+            p, n = superellipsoid(rng, int(counts[k]), c, axes, e1, e2, table)
+        ps.append(p)
+        ns.append(n)
+    p = np.concatenate(ps)
+    n = np.concatenate(ns)
+    perm = rng.permutation(P)
+    p, n = p[perm], n[perm]
+    pj = p + rng.normal(0.0, 0.25 / res, p.shape)
+    return Shape(res, 2.0, _f32(pj), _f32(n), _f32(p), _f32(n), kind="scene", meta=dict(objects=n_objects))
+
+
 def thin_plate(seed: int, P: int, res: int, half_thickness: float = 0.006, table=(256, 512)) -> Shape:
     """A thin closed plate: P points by area on a flat superellipsoid with axes
     (half_thickness, 0.3, 0.3) along grid axes (0, 1, 2) (exponents 0.5 across

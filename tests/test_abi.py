@@ -52,6 +52,27 @@ def test_size_queries_reject_bad_arguments(L, res, P):
     assert L.psr_saved_bytes(res, P, ctypes.byref(out)) == _lib.PSR_EINVAL
 
 
+@pytest.mark.parametrize("res,slabs", [(16, 1), (16, 16), (64, 64), (256, 8), (1024, 8), (1024, 64)])
+def test_slab_workspace_sizes(L, res, slabs):
+    P = 1000
+    out = ctypes.c_size_t(0)
+    assert L.psr_slab_workspace_bytes(res, P, slabs, ctypes.byref(out)) == _lib.PSR_OK
+    hp = res // 2 + 1
+    # three splat channels, two exchange channels, one returned channel
+    assert out.value >= (3 + 2 + 1) * res * res * hp * 8 + P * 80
+    assert out.value % 256 == 0
+    zero = ctypes.c_size_t(0)
+    assert L.psr_slab_workspace_bytes(res, 0, slabs, ctypes.byref(zero)) == _lib.PSR_OK
+    assert zero.value < out.value
+
+
+@pytest.mark.parametrize("res,slabs,P", [(8, 1, 10), (2048, 8, 10), (96, 2, 10), (64, 3, 10), (64, 128, 10),
+                                         (32, 64, 10), (64, 0, 10), (64, 4, -1)])
+def test_slab_size_query_rejects_bad_arguments(L, res, slabs, P):
+    out = ctypes.c_size_t(0)
+    assert L.psr_slab_workspace_bytes(res, P, slabs, ctypes.byref(out)) == _lib.PSR_EINVAL
+
+
 def test_null_arguments_rejected_without_device_work(L):
     # every check below fails before any HIP call is made
     assert L.psr_forward(None, None, None, 10, 64, 2.0, None, None, None, 0, None) == _lib.PSR_EINVAL
@@ -62,6 +83,8 @@ def test_null_arguments_rejected_without_device_work(L):
     assert L.psr_run_batched(None, 1, None, None) == _lib.PSR_EINVAL
     assert L.psr_debug_spectral(None, None, 64, 2.0, None, None, 0, None) == _lib.PSR_EINVAL
     assert L.psr_saved_status(None, None, None) == _lib.PSR_EINVAL
+    assert L.psr_slab_forward(None, None, None, 10, 64, 2.0, 4, None, None, None, 0, None) == _lib.PSR_EINVAL
+    assert L.psr_slab_debug_spectral(None, None, 64, 2.0, 4, None, None, 0, None) == _lib.PSR_EINVAL
 
 
 def test_mc_case_table_matches_the_oracle(L):
