@@ -389,6 +389,88 @@ def batch_c4(dev, torch, steps=10, warmup=3):
             "step_roofline_frac": round(total_bytes / t_b / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def batch_c2(dev, torch, copies=24, steps=10, warmup=3):
+    """The 128^3 workload (20k points, fwd+bwd) as one batch of `copies`
+    solves (one launch per stage for all of them), against the same number
+    of single solves one after the other: a single 128^3 solve leaves most of
+    the 256 CUs idle between its dependent passes, a batch fills them."""
+    import psr_synth as S
+    from paper_2106_03452_amd import function as F
+    from paper_2106_03452_amd.batch import BatchPlan, Job
+    sh = S.config_c2()
+    p = torch.from_numpy(sh.points).to(dev)
+    n = torch.from_numpy(sh.normals).to(dev)
+    chi_t, _ = F.forward(torch.from_numpy(sh.points_clean).to(dev), torch.from_numpy(sh.normals_clean).to(dev),
+                         128, sh.sigma)
+    chi, _ = F.forward(p, n, 128, sh.sigma)
+    G = (2.0 * (chi - chi_t) / chi.numel()).contiguous()
+    plan = BatchPlan([Job(p, n, 128, sh.sigma, G) for _ in range(copies)])
+    dt = timed(plan.run, steps, warmup, torch)
+    t = dt / steps
+    return {"workload": f"{copies} copies of the 128^3 / 20k-point solve, fwd+bwd, one batched call",
+            "solves_per_s": round(copies / t, 1), "ms_per_batch": round(t * 1e3, 4),
+            "dense_equivalent_frac": round(copies * b_stage(128, int(p.shape[0])) / t / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def slab_bytes(r, P):
+    """Algorithmic bytes of each stage of the slab forward (grid traffic with
+    every plane counted, plus the point records): sp = one channel of the
+    half spectrum, r^2 (r/2 + 1) complex64."""
+    sp = r * r * (r // 2 + 1) * 8
+    return {"slab_bin": 112 * P, "S1_splat_r2c": 3 * sp + 192 * P, "S2_fft_j1_exchange": 5 * sp,
+            "S3_pencil_fft_j0_spectral": 3 * sp, "S4_ifft_k1": 2 * sp, "S5_c2r_halo": sp + 4 * r ** 3,
+            "slab_gather_mean": P * (32 + 32 + 8 + 8), "slab_normalize": 8 * r ** 3}
+
+
+def slab_leg(dev, torch, steps=3, warmup=1, slabs=8):
+    """The large-scene form: a 1M-point scene of 16 objects on a 1024^3 grid
+    (sigma 2), forward only, solved in `slabs` slabs of 128 planes; stage
+    times from HIP events on the solve stream. Also the C3 cloud at 256^3
+    through the slab path, beside the single-grid forward of the same cloud."""
+    import psr_synth as S
+    from paper_2106_03452_amd import _lib
+    from paper_2106_03452_amd import slab as SL
+    ctx = _lib.context(0)
+    sh = S.config_scene()
+    r, P = sh.res, sh.P
+    pts = torch.from_numpy(sh.points).to(dev)
+    nrm = torch.from_numpy(sh.normals).to(dev)
+    ws = torch.empty(SL.workspace_bytes(r, P, slabs), dtype=torch.uint8, device=dev)
+    chi = torch.empty((r, r, r), dtype=torch.float32, device=dev)
+    rb = torch.zeros(48, dtype=torch.uint8, device=dev)
+
+    def step():
+        SL.forward_raw(pts, nrm, r, sh.sigma, slabs, chi, rb, ws, ctx)
+    dt = timed(step, steps, warmup, torch)
+    ms = dt / steps * 1e3
+    ctx.set("timers", 1)
+    ctx.reset_timers()
+    timed(step, steps, 0, torch)
+    st = {k: v[0] / v[1] for k, v in ctx.stage_times().items() if v[1] > 0}
+    ctx.set("timers", 0)
+    sb = slab_bytes(r, P)
+    total = sum(sb.values())
+    stages = {k: {"ms": round(st[k], 4), "GBs": round(sb[k] / (st[k] * 1e-3) / 1e9, 1),
+                  "frac": round(sb[k] / (st[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)} for k in sb if k in st}
+    status = SL.read_result(rb)["status"]
+    del ws, chi
+    # the same path on the 256^3 cloud, beside the single-grid forward
+    from paper_2106_03452_amd import function as F
+    c3 = S.config_c3()
+    p3, n3 = torch.from_numpy(c3.points).to(dev), torch.from_numpy(c3.normals).to(dev)
+    ws3 = torch.empty(SL.workspace_bytes(256, c3.P, slabs), dtype=torch.uint8, device=dev)
+    chi3 = torch.empty((256, 256, 256), dtype=torch.float32, device=dev)
+    d3 = timed(lambda: SL.forward_raw(p3, n3, 256, c3.sigma, slabs, chi3, rb, ws3, ctx), 20, 3, torch)
+    wsf = torch.empty(_lib.workspace_bytes(256, c3.P), dtype=torch.uint8, device=dev)
+    d4 = timed(lambda: F.forward(p3, n3, 256, c3.sigma, ctx, wsf), 20, 3, torch)
+    return {"workload": f"1024^3, 1M points on 16 objects (seed 5), sigma 2, forward only, {slabs} slabs of "
+                        f"{r // slabs} planes", "status": status,
+            "ms_per_solve": round(ms, 3), "solves_per_s": round(1e3 / ms, 2),
+            "dense_bytes": total, "dense_GBs": round(total / (ms * 1e-3) / 1e9, 1),
+            "dense_frac": round(total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "stages": stages,
+            "c3_256_slab_ms": round(d3 / 20 * 1e3, 4), "c3_256_single_grid_fwd_ms": round(d4 / 20 * 1e3, 4)}
+
+
 def serve_mode(dev, torch, n_requests, levels=(0.5, 0.8, 1.0, 1.5)):
     """Poisson request stream (seed 4): res in {64,128,256}, P log-uniform in
     [3e3, 2e5], 50/50 forward vs forward+backward. lambda_seq = throughput of
@@ -575,9 +657,10 @@ def main():
                     help="requests of the compact serving leg of the default run (levels 1.0 and 1.5 x lambda_seq)")
     ap.add_argument("--no-serve", action="store_true", help="skip the compact serving leg")
     ap.add_argument("--no-loops", action="store_true", help="skip the optimisation-loop and training-step legs")
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "mc"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "mc", "slab"], default="c3",
                     help="profiling runs: c3 = the headline line (default); c2 = only the 128^3 fwd+bwd steps; "
-                         "c4 = only the 64-shape batch; mc = only Marching Cubes of the 256^3 solve")
+                         "c4 = only the 64-shape batch; mc = only Marching Cubes of the 256^3 solve; "
+                         "slab = only the 1024^3 slab forward")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (scale reference for HBM counters)")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -623,6 +706,8 @@ def main():
             b2 = prepare(S.config_c2(), dev, torch, F)
             dt = timed(make_step(b2, ctx), args.steps, args.warmup, torch)
             print(json.dumps({"workload": "c2", "ms_per_step": round(dt / args.steps * 1e3, 4)}), flush=True)
+        elif args.workload == "slab":
+            print(json.dumps({"workload": "slab", **slab_leg(dev, torch, args.steps, args.warmup)}), flush=True)
         elif args.workload == "c4":
             print(json.dumps({"workload": "c4", **batch_c4(dev, torch, args.steps, args.warmup)}), flush=True)
         else:
@@ -743,7 +828,9 @@ def main():
                                     "ms": round(d1 / (args.steps * 10) * 1e3, 4)}
         del b1
         secondary["batch_c4"] = batch_c4(dev, torch)
+        secondary["batch_128"] = batch_c2(dev, torch)
         secondary["marching_cubes_256"] = marching_cubes_leg(dev, torch, b["chi"])
+        secondary["slab_1024"] = slab_leg(dev, torch)
         if not args.no_loops:
             secondary["optimisation_loop"] = optimisation_leg(dev, torch)
             secondary["training_step_128"] = training_leg(dev, torch)
