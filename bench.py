@@ -154,7 +154,7 @@ KERNEL_STAGES = [
 ]
 
 
-SOLVER_SOURCES = ["fft_device.h", "psr_geometry.h", "psr_internal.h", "psr_kernels.hip"]
+SOLVER_SOURCES = ["fft_device.h", "psr_geometry.h", "psr_internal.h", "psr_device.h", "psr_kernels.hip"]
 
 
 def kernel_source_hash() -> str:
