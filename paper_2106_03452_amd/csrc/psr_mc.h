@@ -26,6 +26,7 @@ constexpr int kMcGroup = 1024;                  // workgroup counts per first-le
 struct McState {
   McHeader* hdr;
   int2* blk;        // per workgroup of the sweeps: counts, then offsets within its scan group (vertices, triangles)
+  int2* cnt;        // per workgroup of the sweeps: its counts (kept through the scan)
   int2* tops;       // per scan group: exclusive offsets
   uint32_t* vbase;  // per grid vertex with a crossing edge: first vertex index << 3 | crossing mask
 };
@@ -41,7 +42,7 @@ struct McOut {
 inline size_t mc_align(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct McLayout {
-  size_t hdr, blk, tops, vbase, total;
+  size_t hdr, blk, cnt, tops, vbase, total;
 };
 
 inline size_t mc_blocks(int res) { return ((size_t)res * res * res + kMcBlock - 1) / kMcBlock; }
@@ -52,7 +53,8 @@ inline McLayout state_layout(int res) {
   McLayout L;
   L.hdr = 0;
   L.blk = mc_align(sizeof(McHeader));
-  L.tops = L.blk + mc_align(mc_blocks(res) * sizeof(int2));
+  L.cnt = L.blk + mc_align(mc_blocks(res) * sizeof(int2));
+  L.tops = L.cnt + mc_align(mc_blocks(res) * sizeof(int2));
   L.vbase = L.tops + mc_align(mc_groups(res) * sizeof(int2));
   L.total = L.vbase + mc_align(n * 4);
   return L;
@@ -64,6 +66,7 @@ inline McState state_view(void* base, int res) {
   McState s;
   s.hdr = reinterpret_cast<McHeader*>(b + L.hdr);
   s.blk = reinterpret_cast<int2*>(b + L.blk);
+  s.cnt = reinterpret_cast<int2*>(b + L.cnt);
   s.tops = reinterpret_cast<int2*>(b + L.tops);
   s.vbase = reinterpret_cast<uint32_t*>(b + L.vbase);
   return s;

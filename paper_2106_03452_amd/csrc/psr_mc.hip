@@ -8,14 +8,16 @@
 //          summed per workgroup (1024 vertices: 4 consecutive ones along j2
 //          per thread, read as float4 rows)
 //   scan   exclusive offsets of the workgroup sums, in two levels
-//   emit   per vertex again: its mesh vertices (position by linear zero along
-//          the edge, normal from the central-difference gradient), the base
-//          index of its vertices, and its cell's triangles as global edge ids
+//   emit   per vertex again, in the workgroups that hold surface only: its
+//          mesh vertices (position by linear zero along the edge, normal from
+//          the central-difference gradient), the base index of its vertices,
+//          and its cell's triangles as global edge ids
 //   link   edge ids of the triangles -> vertex indices
 // Mesh vertices are numbered by global edge id 3 * j + axis, triangles by
 // cell (row-major) and table order: the same order a serial sweep gives.
-// The grid is read twice (count and emit): the emit pass must know where its
-// workgroup's output starts, which only the scan over all workgroups gives.
+// The grid is read once in full (count) and again only where the surface is
+// (emit): the emit pass must know where its workgroup's output starts, which
+// only the scan over all workgroups gives.
 //
 // Backward (main Eq. 6): dp/dchi = -n, spread onto the two ends of each
 // vertex's edge with its interpolation weights (1 - t, t); one thread per
@@ -132,7 +134,10 @@ __global__ __launch_bounds__(kMcThreads) void k_mc_count(const float* __restrict
   }
   int2 tot;
   block_scan2<kMcThreads>(make_int2(nv, nt), wtot, tot);
-  if (threadIdx.x == 0) st.blk[blockIdx.x] = tot;
+  if (threadIdx.x == 0) {
+    st.blk[blockIdx.x] = tot;
+    st.cnt[blockIdx.x] = tot;
+  }
 }
 
 // first level: exclusive offsets of the workgroup counts within groups of
@@ -174,6 +179,12 @@ template <int R>
 __global__ __launch_bounds__(kMcThreads) void k_mc_emit(const float* __restrict__ chi, float iso, McState st,
                                                         McOut out) {
   __shared__ int2 wtot[kMcThreads / 64];
+  {
+    // no surface in this workgroup: nothing to emit, and its part of the
+    // grid is not read again (uniform over the workgroup)
+    const int2 c = st.cnt[blockIdx.x];
+    if (c.x == 0 && c.y == 0) return;
+  }
   const int64_t e = ((int64_t)blockIdx.x * kMcThreads + threadIdx.x) * kMcVpt;
   const bool live = e < (int64_t)R * R * R;
   Run<R> q;
@@ -188,7 +199,6 @@ __global__ __launch_bounds__(kMcThreads) void k_mc_emit(const float* __restrict_
   }
   int2 tot;
   const int2 incl = block_scan2<kMcThreads>(make_int2(nv, nt), wtot, tot);
-  if (tot.x == 0 && tot.y == 0) return;  // no surface in this workgroup (uniform)
   const int2 b = st.blk[blockIdx.x], g = st.tops[blockIdx.x / kMcGroup];
   int v = g.x + b.x + incl.x - nv;
   int64_t tri = (int64_t)g.y + b.y + incl.y - nt;
