@@ -63,11 +63,14 @@ struct SlabLayout {
   size_t hdr, counts, off, bsum, tmp, colrank, sorted, val, red, A, X, Z, halo, total;
 };
 
-// A: the three splat channels after the row pass, A_g[c][j0 - g s][j1][k2]
+// Spectra are k2-tiled: k2 in tiles of tc = slab_cols(r) values, nt = hp / tc
+// tiles, the tc values of a tile innermost, so that a column pass's tile of
+// tc lines is one contiguous block (or a few long runs).
+// A: the three splat channels after the row pass, A_g[c][j0 - g s][nt][j1][tc]
 //    per slab (3 s r hp complex each), later the rows before the c2r pass,
-//    Y_g[j0 - g s][j1][k2] (s r hp each, in the first third of A_g's room);
-// X: blocks (h, g), h-major: [2][s][q][hp] (v~_0 and the merged channel W);
-// Z: blocks (g, h), g-major: [s][q][hp];
+//    Y_g[j0 - g s][nt][j1][tc] (s r hp each, in the first third of A_g's room);
+// X: blocks (h, g), h-major: [2][s][nt][q][tc] (v~_0 and the merged channel W);
+// Z: blocks (g, h), g-major: [s][nt][q][tc];
 // halo: per slab, chi' of the first plane of the next slab (r r floats).
 __host__ __device__ inline SlabLayout slab_layout(int res, int64_t P, int G) {
   const size_t hp = (size_t)slab_hp(res), bins = (size_t)res * res, plane = (size_t)res * hp;

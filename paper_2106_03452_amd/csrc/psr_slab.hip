@@ -6,14 +6,14 @@
 //
 // Slab g owns planes [g s, (g+1) s) of j0 (s = r/G). Per slab:
 //   S1  splat normals into LDS rows (64-bit fixed point, the row splat of
-//       the single-grid solver) + r2c FFT along j2      -> A_g[c][j0][j1][k2]
+//       the single-grid solver) + r2c FFT along j2      -> A_g[c][j0][k2 tile][j1]
 //   S2  FFT along j1; channels 1, 2 merged into W = kappa_1 v~_1 + kappa_2 v~_2;
 //       each k1 range goes to its pencil owner         -> X blocks (h, g)
 // Per pencil owner h (k1 in [h q, (h+1) q)):
 //   S3  FFT along j0 of v~_0 and W, spectral operator of main Eq. 3, inverse
 //       FFT along k0; each j0 range back to its slab   -> Z blocks (g, h)
 // Per slab:
-//   S4  inverse FFT along k1                           -> Y_g[j0][j1][k2]
+//   S4  inverse FFT along k1                           -> Y_g[j0][k2 tile][j1]
 //   S5  c2r FFT along k2: chi' rows; the slab's first plane also goes to the
 //       previous slab's halo
 //   gather: chi' at the points whose floor plane lies in the slab (the top
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(256) void k_slab_scatter(SlabArgs a) {
 
 // ---------------------------------------------------------------------------
 // S1: rows of one plane of slab g (one channel) -> LDS splat (or the test
-// field) -> r2c FFT along j2 -> A_g[c][j0 - g s][j1][k2], rows of r/2 + 1.
+// field) -> r2c FFT along j2 -> A_g[c][j0 - g s], k2-tiled rows of r/2 + 1.
 // ---------------------------------------------------------------------------
 template <int RES, bool LOAD>
 __global__ __launch_bounds__(slab_rows_block(RES)) void k_slab_rows_fwd(const SlabArgs a, int g) {
@@ -258,13 +258,19 @@ __global__ __launch_bounds__(slab_rows_block(RES)) void k_slab_rows_fwd(const Sl
   const int s = RES / a.G;
   const int T = blockIdx.x % (s * NT), c = blockIdx.x / (s * NT);
   const int j0l = T / NT, a0 = (T % NT) * TR, j0 = g * s + j0l;
-  cf* const out = a.A + ((int64_t)(3 * g + c) * s + j0l) * RES * HP + (int64_t)a0 * HP;
+  constexpr int TC = slab_cols(RES);
+  // k2-tiled plane: element (j1, k2) at ((k2 / TC) RES + j1) TC + k2 % TC; the
+  // loops below run tile by tile, so each tile's TR rows are one contiguous run
+  cf* const out = a.A + ((int64_t)(3 * g + c) * s + j0l) * RES * HP + (int64_t)a0 * TC;
   const int t = threadIdx.x;
   Ranges R{};
   if constexpr (!LOAD) {
     R = slab_ranges<RES, TR>(a.off, j0, a0);
     if (R.total == 0) {  // no point reaches these rows: their spectra are zero
-      for (int e = t; e < TR * H; e += BR) out[(e / H) * HP + e % H] = cf{0.0f, 0.0f};
+      for (int e = t; e < TR * HP; e += BR) {
+        const int kk = e % TC, l = (e / TC) % TR, kt = e / (TC * TR);
+        if (kt * TC + kk < H) out[((int64_t)kt * RES + l) * TC + kk] = cf{0.0f, 0.0f};
+      }
       return;
     }
   }
@@ -277,20 +283,21 @@ __global__ __launch_bounds__(slab_rows_block(RES)) void k_slab_rows_fwd(const Sl
     fft<M, -1, false, false>(reg, rows + l * LS, t % TPL, stw, row_swz(M, l));
   }
   // X[k] = E_k + W_r^k O_k with E = (Z_k + Z*_{M-k})/2, O = (Z_k - Z*_{M-k})/(2i)
-  for (int e = t; e < TR * H; e += BR) {
-    const int l = e / H, k = e % H;
+  for (int e = t; e < TR * HP; e += BR) {
+    const int kk = e % TC, l = (e / TC) % TR, kt = e / (TC * TR), k = kt * TC + kk;
+    if (k >= H) continue;
     const cf zk = rows[rpos<M>(l, k == M ? 0 : k)];
     const cf zm = rows[rpos<M>(l, k == 0 ? 0 : M - k)];
     const cf Ee{0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y)};
     const cf Oo{0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x)};
-    out[l * HP + k] = cadd(Ee, cmul(rtw[k], Oo));
+    out[((int64_t)kt * RES + l) * TC + kk] = cadd(Ee, cmul(rtw[k], Oo));
   }
 }
 
 // ---------------------------------------------------------------------------
 // S2: FFT along j1 of slab g. Output channel 0 = v~_0, channel 1 =
 // W = kappa_1(k1) v~_1 + kappa_2(k2) v~_2 (all the j0 pass needs of channels
-// 1 and 2); element k1 goes to block (k1 / q, g): [2][s][q][hp].
+// 1 and 2); element k1 goes to block (k1 / q, g): [2][s][nt][q][tc].
 // ---------------------------------------------------------------------------
 template <int RES>
 __global__ __launch_bounds__(slab_cols_block(RES)) void k_slab_fft_j1(const SlabArgs a, const BlockPtrs dst, int g) {
@@ -310,19 +317,20 @@ __global__ __launch_bounds__(slab_cols_block(RES)) void k_slab_fft_j1(const Slab
   const int k2a = kt * TC, nvalid = H - k2a;
   const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
   const int64_t CH = (int64_t)s * RES * HP;
-  const cf* src = a.A + ((int64_t)3 * g * s + j0l) * RES * HP + k2a;
+  // the tile of channel 0 (k2-tiled planes: one contiguous RES x TC block)
+  const cf* src = a.A + ((int64_t)3 * g * s + j0l) * RES * HP + (int64_t)kt * RES * TC;
   cf reg[E];
   if (oc == 0) {
-    load_cols<RES, TC>(rows, [&](int n) { return src + (int64_t)n * HP; }, nvalid);
+    load_cols<RES, TC>(rows, [&](int n) { return src + (int64_t)n * TC; }, nvalid);
     fft<RES, -1, false, true>(reg, rows + l * LS, lt, stw);
   } else {
     cf acc[E];
-    load_cols<RES, TC>(rows, [&](int n) { return src + 2 * CH + (int64_t)n * HP; }, nvalid);
+    load_cols<RES, TC>(rows, [&](int n) { return src + 2 * CH + (int64_t)n * TC; }, nvalid);
     fft<RES, -1, false, true>(reg, rows + l * LS, lt, stw);
     const float k2f = kappa_odd(k2a + l, RES);
 #pragma unroll
     for (int v = 0; v < E; ++v) acc[v] = cscale(reg[v], k2f);
-    load_cols<RES, TC>(rows, [&](int n) { return src + CH + (int64_t)n * HP; }, nvalid);
+    load_cols<RES, TC>(rows, [&](int n) { return src + CH + (int64_t)n * TC; }, nvalid);
     fft<RES, -1, false, true>(reg, rows + l * LS, lt, stw);
 #pragma unroll
     for (int v = 0; v < E; ++v) {
@@ -332,14 +340,15 @@ __global__ __launch_bounds__(slab_cols_block(RES)) void k_slab_fft_j1(const Slab
   }
   store_cols<RES, TC>(
       rows, reg, l, lt,
-      [&](int n) { return dp[n >> lq] + ((int64_t)(oc * s + j0l) * q + (n & (q - 1))) * HP + k2a; }, nvalid);
+      [&](int n) { return dp[n >> lq] + (((int64_t)(oc * s + j0l) * NKT + kt) * q + (n & (q - 1))) * TC; },
+      nvalid);
 }
 
 // ---------------------------------------------------------------------------
 // S3: pencil owner h, line (k1, k2) over all j0: FFT along j0 of v~_0 and W,
 // chi~ = i F(k) (kappa_0(k0) v~_0 + W) (main Eq. 3, the inverse's 1/N folded
 // into F), inverse FFT along k0; element j0 goes to block (j0 / s, h):
-// [s][q][hp].
+// [s][nt][q][tc].
 // ---------------------------------------------------------------------------
 template <int RES>
 __global__ __launch_bounds__(slab_cols_block(RES)) void k_slab_pencil_j0(const SlabArgs a, const BlockPtrs src,
@@ -364,13 +373,14 @@ __global__ __launch_bounds__(slab_cols_block(RES)) void k_slab_pencil_j0(const S
   const int k1 = h * q + k1l;
   const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
   cf acc[E], reg[E];
-  load_cols<RES, TC>(rows, [&](int n) { return sp[n >> ls] + ((int64_t)(n & (s - 1)) * q + k1l) * HP + k2a; },
-                     nvalid);
+  load_cols<RES, TC>(
+      rows, [&](int n) { return sp[n >> ls] + (((int64_t)(n & (s - 1)) * NKT + kt) * q + k1l) * TC; }, nvalid);
   fft<RES, -1, false, true>(reg, rows + l * LS, lt, stw);
 #pragma unroll
   for (int v = 0; v < E; ++v) acc[v] = cscale(reg[v], kappa_odd(lt + TPL * v, RES));
   load_cols<RES, TC>(
-      rows, [&](int n) { return sp[n >> ls] + ((int64_t)(s + (n & (s - 1))) * q + k1l) * HP + k2a; }, nvalid);
+      rows, [&](int n) { return sp[n >> ls] + (((int64_t)(s + (n & (s - 1))) * NKT + kt) * q + k1l) * TC; },
+      nvalid);
   fft<RES, -1, false, true>(reg, rows + l * LS, lt, stw);
   {
     const int k2 = imin(k2a + l, M);  // padding lines are zero; any finite factor will do
@@ -385,11 +395,12 @@ __global__ __launch_bounds__(slab_cols_block(RES)) void k_slab_pencil_j0(const S
   }
   fft<RES, +1, true, true>(reg, rows + l * LS, lt, stw);
   store_cols<RES, TC>(
-      rows, reg, l, lt, [&](int n) { return dp[n >> ls] + ((int64_t)(n & (s - 1)) * q + k1l) * HP + k2a; }, nvalid);
+      rows, reg, l, lt, [&](int n) { return dp[n >> ls] + (((int64_t)(n & (s - 1)) * NKT + kt) * q + k1l) * TC; },
+      nvalid);
 }
 
 // ---------------------------------------------------------------------------
-// S4: inverse FFT along k1 of slab g, from blocks (g, h) -> Y_g[j0][j1][k2].
+// S4: inverse FFT along k1 of slab g, from blocks (g, h) -> Y_g[j0], k2-tiled.
 // ---------------------------------------------------------------------------
 template <int RES>
 __global__ __launch_bounds__(slab_cols_block(RES)) void k_slab_ifft_k1(const SlabArgs a, const BlockPtrs src, int g) {
@@ -406,11 +417,11 @@ __global__ __launch_bounds__(slab_cols_block(RES)) void k_slab_ifft_k1(const Sla
   const int k2a = kt * TC, nvalid = H - k2a;
   const int l = threadIdx.x / TPL, lt = threadIdx.x % TPL;
   cf reg[E];
-  load_cols<RES, TC>(rows, [&](int n) { return sp[n >> lq] + ((int64_t)j0l * q + (n & (q - 1))) * HP + k2a; },
-                     nvalid);
+  load_cols<RES, TC>(
+      rows, [&](int n) { return sp[n >> lq] + (((int64_t)j0l * NKT + kt) * q + (n & (q - 1))) * TC; }, nvalid);
   fft<RES, +1, false, true>(reg, rows + l * LS, lt, stw);
-  cf* const y = a.A + (int64_t)(g * s + j0l) * RES * HP + k2a;
-  store_cols<RES, TC>(rows, reg, l, lt, [&](int n) { return y + (int64_t)n * HP; }, nvalid);
+  cf* const y = a.A + (int64_t)(g * s + j0l) * RES * HP + (int64_t)kt * RES * TC;
+  store_cols<RES, TC>(rows, reg, l, lt, [&](int n) { return y + (int64_t)n * TC; }, nvalid);
 }
 
 // ---------------------------------------------------------------------------
@@ -429,10 +440,11 @@ __global__ __launch_bounds__(slab_rows_block(RES)) void k_slab_rows_inv(const Sl
   const int t = threadIdx.x;
   stage_table<BR>(stw, a.tw + M, M);
   stage_table<BR>(rtw, a.tw + RES, M + 1);
-  const cf* in = a.A + ((int64_t)(g * s + j0l) * RES + a0) * HP;
-  for (int e = t; e < TR * H; e += BR) {
-    const int l = e / H, k = e % H;
-    rows[rpos<M>(l, k)] = in[l * HP + k];
+  constexpr int TC = slab_cols(RES);
+  const cf* in = a.A + (int64_t)(g * s + j0l) * RES * HP + (int64_t)a0 * TC;  // k2-tiled plane
+  for (int e = t; e < TR * HP; e += BR) {
+    const int kk = e % TC, l = (e / TC) % TR, kt = e / (TC * TR), k = kt * TC + kk;
+    if (k < H) rows[rpos<M>(l, k)] = in[((int64_t)kt * RES + l) * TC + kk];
   }
   __syncthreads();
   // Hermitian half-spectrum X[0..M] -> packed spectrum Z[0..M) of the
