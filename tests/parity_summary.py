@@ -7,8 +7,10 @@ this file is the record of the numbers they check).
 Workloads: the 32^3 sphere (forward), the 128^3 torus + sphere with its
 finite-difference entries, the same with half the points outliers, the 256^3
 superellipsoid, the 256^3 cloud on 512^3 against stored oracle samples, the
-thin closed plate at 64^3 and 128^3, and each of the 64 shapes of the
-batched workload solved in one batch. Metrics: e_chi = max|chi_gpu -
+thin closed plate at 64^3 and 128^3, each of the 64 shapes of the batched
+workload solved in one batch, and the slab-decomposed forward (256^3 against
+the oracle, 512^3 against the stored samples, one Fourier mode at 1024^3
+against its closed form). Metrics: e_chi = max|chi_gpu -
 chi_ref| / max|chi_ref|, e_dpoints and e_dnormals = relative L2 error; bars
 1e-5 and 1e-4. Each side forms its own loss gradient (G = 2 (chi - chi_t) / N
 for the benchmark losses, G = 2 chi / N for the batch).
@@ -130,6 +132,38 @@ def main(path):
                     "e_dpoints": l2_rel(host(dp_b), dc_r), "e_dnormals": l2_rel(host(dn_b), dn_r)})
     W["c4_batch_per_shape"] = {"shapes": per, "max": {k: max(q[k] for q in per)
                                                       for k in ("e_chi", "e_dpoints", "e_dnormals")}}
+    # the slab-decomposed forward: the 256^3 workload in 8 slabs against the
+    # oracle, the same cloud on 512^3 in 4 slabs against the stored samples,
+    # and one Fourier mode on 1024^3 in 8 slabs against its closed form
+    from paper_2106_03452_amd import slab as SL
+    say("slab forward 256^3 / 8 slabs")
+    sh = S.config_c3()
+    chi, sc = SL.forward(to_dev(sh.points, dev), to_dev(sh.normals, dev), 256, sh.sigma, 8)
+    ref, aux = oracle.forward(sh.points, sh.normals, 256, sh.sigma)
+    W["slab_c3_256_8"] = {"res": 256, "npoints": sh.P, "slabs": 8, "status": sc["status"],
+                          "e_chi": max_rel(host(chi), ref)}
+    say("slab forward 512^3 / 4 slabs vs stored oracle samples")
+    chi, sc = SL.forward(to_dev(sh.points, dev), to_dev(sh.normals, dev), 512, sh.sigma, 4)
+    chi_s = host(chi.reshape(-1)[torch.as_tensor(g["vox"], device=dev)])
+    W["slab_c3_cloud_512_samples"] = {"res": 512, "npoints": sh.P, "slabs": 4, "status": sc["status"],
+                                      "e_chi": float(np.abs(chi_s - g["chi"]).max() / float(g["chi_max"]))}
+    del chi
+    say("slab spectral closed form 1024^3 / 8 slabs")
+    res, sigma, k, d = 1024, 2.0, (100, -3, 201), 2
+    j = torch.arange(res, device=dev, dtype=torch.float64) * (2 * np.pi / res)
+    th = k[0] * j[:, None, None] + k[1] * j[None, :, None] + k[2] * j[None, None, :]
+    v = torch.zeros((3, res, res, res), dtype=torch.float32, device=dev)
+    v[d] = torch.cos(th).float()
+    K2 = float(np.dot(k, k))
+    expect = torch.sin(th)
+    del th
+    expect *= np.exp(-2 * sigma ** 2 * K2 / res ** 2) * k[d] / (2 * np.pi * K2)
+    outp = SL.debug_spectral(v, sigma, 8)
+    del v
+    W["slab_mode_1024_8"] = {"res": res, "slabs": 8, "mode": list(k), "channel": d,
+                             "e_chi": float((outp.double() - expect).abs().max() / expect.abs().max())}
+    del outp, expect
+    torch.cuda.empty_cache()
     out["seconds"] = round(time.time() - t0, 1)
     worst = {}
     for name, w in W.items():
