@@ -114,6 +114,21 @@ def main(path):
     for res in (64, 128):
         say(f"thin plate {res}^3")
         W[f"thin_plate_{res}"] = run_pair(F, S.thin_plate(7, 60000, res), dev)
+    # clouds with random normals: |c| small against max|chi'|, so chi carries
+    # chi''s FP32 error amplified by a = max|chi| / m (chi' and c keep 1e-5)
+    for res, P in ((16, 600000), (64, 10007)):
+        say(f"random normals {res}^3, {P} points")
+        sh = S.tiny_case(7 * res + P, res, P, 2.0, kind="uniform")
+        chi, saved = F.forward(to_dev(sh.points, dev), to_dev(sh.normals, dev), res, 2.0)
+        ref, aux = oracle.forward(sh.points, sh.normals, res, 2.0)
+        sc = F.scalars(saved)
+        chip = host(chi) / sc["scale"] + sc["mean"]
+        W[f"random_normals_{res}_{P}"] = {
+            "res": res, "npoints": P, "status": F.status(saved),
+            "e_chi_prime": max_rel(chip, aux["chi_prime"]),
+            "e_c": abs(sc["cscale"] - aux["cscale"]) / np.abs(aux["chi_prime"]).max(),
+            "e_chi_amplified": max_rel(host(chi), ref),
+            "amplification": max(1.0, float(np.abs(ref).max() / aux["m"]))}
     say("64-shape batch, per shape")
     shapes = S.config_c4()
     jobs = []

@@ -48,9 +48,11 @@ def assert_forward_close(psr, chi, saved, ref, aux):
     chip_g = chi_g / sc["scale"] + sc["mean"]
     span = np.abs(aux["chi_prime"]).max()
     amp = max(1.0, np.abs(ref).max() / aux["m"])
-    assert max_rel(chip_g, aux["chi_prime"]) < E_CHI
+    e_p, e_c = max_rel(chip_g, aux["chi_prime"]), max_rel(chi_g, ref)
+    print(f"e_chi'={e_p:.2e} e_chi={e_c:.2e} amplification a={amp:.2f} (chi bar {E_CHI * amp:.1e})")
+    assert e_p < E_CHI
     assert abs(sc["cscale"] - aux["cscale"]) < E_CHI * span
-    assert max_rel(chi_g, ref) < E_CHI * amp
+    assert e_c < E_CHI * amp
 
 
 # ------------------------------------------------------------------ stages
