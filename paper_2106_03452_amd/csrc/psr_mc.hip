@@ -200,45 +200,97 @@ __global__ __launch_bounds__(kMcThreads) void k_mc_emit(const float* __restrict_
   int2 tot;
   const int2 incl = block_scan2<kMcThreads>(make_int2(nv, nt), wtot, tot);
   const int2 b = st.blk[blockIdx.x], g = st.tops[blockIdx.x / kMcGroup];
-  int v = g.x + b.x + incl.x - nv;
-  int64_t tri = (int64_t)g.y + b.y + incl.y - nt;
-  const float inv_r = 1.0f / (float)R;
+  // The workgroup's mesh vertices and triangles are numbered in thread order
+  // (then run position, then axis or table order); they are handed out one
+  // per thread, so that a thread with many does not hold up the workgroup.
+  // Each thread publishes its first indices and its masks / cell cases.
+  __shared__ int pv[kMcThreads], pt[kMcThreads], pm[kMcThreads], pc[kMcThreads];
+  const int t = threadIdx.x;
+  pv[t] = incl.x - nv;
+  pt[t] = incl.y - nt;
+  pm[t] = m[0] | (m[1] << 3) | (m[2] << 6) | (m[3] << 9);
+  pc[t] = cs[0] | (cs[1] << 8) | (cs[2] << 16) | (cs[3] << 24);
+  {
+    int v = g.x + b.x + incl.x - nv;
 #pragma unroll
-  for (int k = 0; k < kMcVpt; ++k) {
-    const int64_t ek = e + k;
-    if (m[k]) st.vbase[ek] = ((uint32_t)v << 3) | (uint32_t)m[k];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (!((m[k] >> a) & 1)) continue;
-      if (v < out.vcap) {
-        const float c0 = q.v[0][0][k];
-        const float cb = a == 0 ? q.v[1][0][k] : (a == 1 ? q.v[0][1][k] : q.v[0][0][k + 1]);
-        const float t = (c0 - iso) / (c0 - cb);
-        const int j2 = q.j2 + k;
-        const float3 ga = grad_at<R>(chi, q.j0, q.j1, j2);
-        const float3 gb = grad_at<R>(chi, q.j0 + (a == 0), q.j1 + (a == 1), j2 + (a == 2));
-        float n0 = (1.0f - t) * ga.x + t * gb.x, n1 = (1.0f - t) * ga.y + t * gb.y, n2 = (1.0f - t) * ga.z + t * gb.z;
-        const float il = rsqrtf(n0 * n0 + n1 * n1 + n2 * n2);
-        out.verts[3 * (int64_t)v + 0] = ((float)q.j0 + (a == 0 ? t : 0.0f)) * inv_r;
-        out.verts[3 * (int64_t)v + 1] = ((float)q.j1 + (a == 1 ? t : 0.0f)) * inv_r;
-        out.verts[3 * (int64_t)v + 2] = ((float)j2 + (a == 2 ? t : 0.0f)) * inv_r;
-        out.normals[3 * (int64_t)v + 0] = n0 * il;
-        out.normals[3 * (int64_t)v + 1] = n1 * il;
-        out.normals[3 * (int64_t)v + 2] = n2 * il;
-        if (out.edges) out.edges[v] = (int32_t)(3 * ek + a);
-      }
-      ++v;
+    for (int k = 0; k < kMcVpt; ++k) {
+      if (m[k]) st.vbase[e + k] = ((uint32_t)v << 3) | (uint32_t)m[k];
+      v += __popc(m[k]);
     }
-    const int n = kTable.ntri[cs[k]];
-    for (int i = 0; i < n; ++i, ++tri) {
-      if (tri >= out.tcap) continue;
+  }
+  __syncthreads();
+  static_assert(kMcVpt == 4 && kMcThreads == 256, "masks and cases packed for 4 vertices per thread");
+  // the thread whose range [p[o], p[o] + count) holds local index x: the last
+  // o with p[o] <= x (threads with nothing share their successor's start)
+  auto owner = [](const int* p, int x) {
+    int lo = 0;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int le = kTable.edge[cs[k]][3 * i + c];
-        // owner of the edge: this vertex plus the lower corner of local edge le
-        const int64_t owner = ek + (int64_t)edge_lo(le, 0) * R * R + edge_lo(le, 1) * R + edge_lo(le, 2);
-        out.tris[3 * tri + c] = (int32_t)(3 * owner + edge_axis(le));
+    for (int step = kMcThreads / 2; step > 0; step >>= 1)
+      if (p[lo + step] <= x) lo += step;
+    return lo;
+  };
+  const float inv_r = 1.0f / (float)R;
+  constexpr int L = __builtin_ctz(R);
+  const int64_t e_blk = (int64_t)blockIdx.x * kMcThreads * kMcVpt;
+  for (int x = t; x < tot.x; x += kMcThreads) {
+    const int v = g.x + b.x + x;
+    if (v >= out.vcap) break;
+    const int o = owner(pv, x);
+    int r = x - pv[o], k = 0, a = 0;
+    const int mo = pm[o];
+    // the r-th crossing edge of the owner, in run-position then axis order
+#pragma unroll
+    for (int kk = 0; kk < kMcVpt; ++kk)
+#pragma unroll
+      for (int aa = 0; aa < 3; ++aa)
+        if ((mo >> (3 * kk + aa)) & 1) {
+          if (r == 0) {
+            k = kk;
+            a = aa;
+          }
+          --r;
+        }
+    const int64_t ek = e_blk + (int64_t)o * kMcVpt + k;
+    const int j2 = (int)(ek & (R - 1)), j1 = (int)((ek >> L) & (R - 1)), j0 = (int)(ek >> (2 * L));
+    const int64_t stride = a == 0 ? (int64_t)R * R : (a == 1 ? R : 1);
+    const float c0 = chi[ek], cb = chi[ek + stride];
+    const float tt = (c0 - iso) / (c0 - cb);
+    const float3 ga = grad_at<R>(chi, j0, j1, j2);
+    const float3 gb = grad_at<R>(chi, j0 + (a == 0), j1 + (a == 1), j2 + (a == 2));
+    const float n0 = (1.0f - tt) * ga.x + tt * gb.x, n1 = (1.0f - tt) * ga.y + tt * gb.y,
+                n2 = (1.0f - tt) * ga.z + tt * gb.z;
+    const float il = rsqrtf(n0 * n0 + n1 * n1 + n2 * n2);
+    out.verts[3 * (int64_t)v + 0] = ((float)j0 + (a == 0 ? tt : 0.0f)) * inv_r;
+    out.verts[3 * (int64_t)v + 1] = ((float)j1 + (a == 1 ? tt : 0.0f)) * inv_r;
+    out.verts[3 * (int64_t)v + 2] = ((float)j2 + (a == 2 ? tt : 0.0f)) * inv_r;
+    out.normals[3 * (int64_t)v + 0] = n0 * il;
+    out.normals[3 * (int64_t)v + 1] = n1 * il;
+    out.normals[3 * (int64_t)v + 2] = n2 * il;
+    if (out.edges) out.edges[v] = (int32_t)(3 * ek + a);
+  }
+  for (int x = t; x < tot.y; x += kMcThreads) {
+    const int64_t tri = (int64_t)g.y + b.y + x;
+    if (tri >= out.tcap) break;
+    const int o = owner(pt, x);
+    const int co = pc[o];
+    // the cell and the table triangle of the owner's (x - pt[o])-th triangle
+    int cell = 0, i = x - pt[o];
+#pragma unroll
+    for (int kk = 0; kk < kMcVpt - 1; ++kk) {
+      const int n = kTable.ntri[(co >> (8 * kk)) & 255];
+      if (cell == kk && i >= n) {
+        i -= n;
+        cell = kk + 1;
       }
+    }
+    const int csk = (co >> (8 * cell)) & 255;
+    const int64_t ek = e_blk + (int64_t)o * kMcVpt + cell;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int le = kTable.edge[csk][3 * i + c];
+      // owner of the edge: this vertex plus the lower corner of local edge le
+      const int64_t own = ek + (int64_t)edge_lo(le, 0) * R * R + edge_lo(le, 1) * R + edge_lo(le, 2);
+      out.tris[3 * tri + c] = (int32_t)(3 * own + edge_axis(le));
     }
   }
 }
