@@ -471,6 +471,45 @@ def slab_leg(dev, torch, steps=3, warmup=1, slabs=8):
             "c3_256_slab_ms": round(d3 / 20 * 1e3, 4), "c3_256_single_grid_fwd_ms": round(d4 / 20 * 1e3, 4)}
 
 
+def sweep(dev, torch):
+    """Sizes beyond the named workloads: the C3 superellipsoid (seed 2) with
+    10^4, 10^5 and 10^6 points at 64^3 to 512^3 (forward + backward, the loss
+    gradient a dense standard normal field, and forward alone), and the
+    1M-point scene at 1024^3 through the slab forward with 2, 8 and 32 slabs."""
+    import psr_synth as S
+    from paper_2106_03452_amd import _lib
+    from paper_2106_03452_amd import function as F
+    from paper_2106_03452_amd import slab as SL
+    ctx = _lib.context(0)
+    rows = []
+    for P in (10_000, 100_000, 1_000_000):
+        base = S.config_c3(P=P)
+        for r in (64, 128, 256, 512):
+            sh = S.Shape(r, 2.0, base.points, base.normals, kind="superellipsoid")
+            b = prepare(sh, dev, torch, F)
+            b["G"] = torch.from_numpy(S.loss_gradient(r, 11)).to(dev)
+            n = 20 if r <= 256 else 5
+            t_fb = timed(make_step(b, ctx), n, 3, torch) / n
+            t_f = timed(make_step(b, ctx, backward=False), n, 3, torch) / n
+            rows.append({"res": r, "npoints": P, "fwd_bwd_ms": round(t_fb * 1e3, 4), "fwd_ms": round(t_f * 1e3, 4),
+                         "fwd_bwd_solves_per_s": round(1.0 / t_fb, 1),
+                         "dense_equivalent_frac": round(b_stage(r, P) / t_fb / 1e9 / HBM_PEAK_GBS, 4)})
+            print(json.dumps(rows[-1]), flush=True)
+            del b
+    sc = S.config_scene()
+    p, n = torch.from_numpy(sc.points).to(dev), torch.from_numpy(sc.normals).to(dev)
+    chi = torch.empty((sc.res,) * 3, dtype=torch.float32, device=dev)
+    rb = torch.zeros(48, dtype=torch.uint8, device=dev)
+    slabs = []
+    for g in (2, 8, 32):
+        ws = torch.empty(SL.workspace_bytes(sc.res, sc.P, g), dtype=torch.uint8, device=dev)
+        t = timed(lambda: SL.forward_raw(p, n, sc.res, sc.sigma, g, chi, rb, ws, ctx), 3, 1, torch) / 3
+        slabs.append({"res": sc.res, "npoints": sc.P, "slabs": g, "fwd_ms": round(t * 1e3, 3)})
+        print(json.dumps(slabs[-1]), flush=True)
+        del ws
+    return {"grid": rows, "slab_1024": slabs}
+
+
 def serve_mode(dev, torch, n_requests, levels=(0.5, 0.8, 1.0, 1.5)):
     """Poisson request stream (seed 4): res in {64,128,256}, P log-uniform in
     [3e3, 2e5], 50/50 forward vs forward+backward. lambda_seq = throughput of
@@ -657,10 +696,11 @@ def main():
                     help="requests of the compact serving leg of the default run (levels 1.0 and 1.5 x lambda_seq)")
     ap.add_argument("--no-serve", action="store_true", help="skip the compact serving leg")
     ap.add_argument("--no-loops", action="store_true", help="skip the optimisation-loop and training-step legs")
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "mc", "slab"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "mc", "slab", "sweep"], default="c3",
                     help="profiling runs: c3 = the headline line (default); c2 = only the 128^3 fwd+bwd steps; "
                          "c4 = only the 64-shape batch; mc = only Marching Cubes of the 256^3 solve; "
-                         "slab = only the 1024^3 slab forward")
+                         "slab = only the 1024^3 slab forward; sweep = grid sizes 64-512 x 1e4-1e6 points "
+                         "and the 1024^3 slab forward at 2, 8, 32 slabs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (scale reference for HBM counters)")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -706,6 +746,8 @@ def main():
             b2 = prepare(S.config_c2(), dev, torch, F)
             dt = timed(make_step(b2, ctx), args.steps, args.warmup, torch)
             print(json.dumps({"workload": "c2", "ms_per_step": round(dt / args.steps * 1e3, 4)}), flush=True)
+        elif args.workload == "sweep":
+            print(json.dumps({"workload": "sweep", **sweep(dev, torch)}), flush=True)
         elif args.workload == "slab":
             print(json.dumps({"workload": "slab", **slab_leg(dev, torch, args.steps, args.warmup)}), flush=True)
         elif args.workload == "c4":

@@ -75,20 +75,47 @@ __device__ __forceinline__ void fetch_recs(Recs<K>& r, const PointRec* __restric
 }
 
 // f(a, b, s) for every point this thread takes: the fetched ones, then any
-// beyond K * BLOCK loaded on the way.
-template <int K, int BLOCK, typename F>
+// beyond K * BLOCK loaded on the way, KT at a time (their loads in flight
+// together; KT = 0: one at a time, for kernels without registers to spare).
+template <int K, int BLOCK, int KT = 0, typename F>
 __device__ __forceinline__ void for_recs(const Recs<K>& r, const PointRec* __restrict__ sorted, const Ranges& R,
                                          int t, F&& f) {
 #pragma unroll
   for (int k = 0; k < K; ++k)
     if (t + k * BLOCK < R.total) f(r.a[k], r.b[k], r.s[k]);
-  for (int q = t + K * BLOCK; q < R.total; q += BLOCK) {
-    float4 a, b;
-    const int64_t s = range_pick(R, q);
-    load_rec(sorted, s, a, b);
-    f(a, b, s);
+  if constexpr (KT == 0) {
+    for (int q = t + K * BLOCK; q < R.total; q += BLOCK) {
+      float4 a, b;
+      const int64_t s = range_pick(R, q);
+      load_rec(sorted, s, a, b);
+      f(a, b, s);
+    }
+  } else {
+    for (int q0 = t + K * BLOCK; q0 < R.total; q0 += KT * BLOCK) {
+      Recs<KT> c;
+#pragma unroll
+      for (int k = 0; k < KT; ++k) {
+        const int q = q0 + k * BLOCK;
+        c.s[k] = 0;
+        c.a[k] = make_float4(0, 0, 0, 0);
+        c.b[k] = c.a[k];
+        if (q < R.total) {
+          c.s[k] = range_pick(R, q);
+          load_rec(sorted, c.s[k], c.a[k], c.b[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < KT; ++k)
+        if (q0 + k * BLOCK < R.total) f(c.a[k], c.b[k], c.s[k]);
+    }
   }
 }
+
+// Records fetched together in the tail of the splat's and gathers' point
+// loops (beyond the first K * BLOCK, so only where a span is dense): none at
+// 256^3 and 512^3, whose row passes have no registers to spare below the
+// 128 that two workgroups per CU allow.
+__host__ __device__ constexpr int rec_tail(int res) { return res >= 256 ? 0 : 2; }
 
 // Fixed-point splat. LDS float atomics are several times slower than integer
 // ones on gfx950, and their result depends on the order of the adds, so the
@@ -214,7 +241,7 @@ __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__
     float m = 1.0f;
     if constexpr (KIND == 0) {
       m = 0.0f;
-      for_recs<KR, BLOCK>(recs, sorted, R, t, [&](const float4&, const float4& p1, int64_t) {
+      for_recs<KR, BLOCK, rec_tail(RES)>(recs, sorted, R, t, [&](const float4&, const float4& p1, int64_t) {
         m = fmaxf(m, fabsf(ch == 0 ? p1.x : (ch == 1 ? p1.y : p1.z)));
       });
     }
@@ -226,7 +253,7 @@ __device__ __forceinline__ void fill_rows(cf* rows, const PointRec* __restrict__
     const float alpha = KIND == 1 ? sqa.z : 1.0f;
 #pragma unroll 1
     for (int par = 0; par < 2; ++par) {
-      for_recs<KR, BLOCK>(recs, sorted, R, t, [&](const float4& p0, const float4& p1, int64_t) {
+      for_recs<KR, BLOCK, rec_tail(RES)>(recs, sorted, R, t, [&](const float4& p0, const float4& p1, int64_t) {
         const uint32_t bb = __float_as_uint(p0.w);
         const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
         float val;

@@ -1018,7 +1018,7 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
     }
   }
   if constexpr (MODE != MODE_DBG) {
-    for_recs<KR, BR>(recs, sorted, R, t, [&](const float4& p0, const float4& p1, int64_t s) {
+    for_recs<KR, BR, rec_tail(RES)>(recs, sorted, R, t, [&](const float4& p0, const float4& p1, int64_t s) {
       const uint32_t bb = __float_as_uint(p0.w);
       const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
       const int n0 = b2, n1 = (b2 + 1) & (RES - 1);
@@ -1402,13 +1402,13 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
     }
   }
   if constexpr (MODE != PI_DBG) {
-    for (int qd = t; qd < total; qd += BLOCK) {
-      int64_t s = pre_s;
-      float4 p0 = pre0, p1 = pre1;
-      if (qd != t) {
-        s = range_pick(R, qd);
-        load_rec(sorted, s, p0, p1);
-      }
+    // the thread's first record was fetched before the row phase; the rest
+    // come in chunks, their loads in flight together
+    Recs<1> first;
+    first.a[0] = pre0;
+    first.b[0] = pre1;
+    first.s[0] = pre_s;
+    for_recs<1, BLOCK, rec_tail(RES)>(first, sorted, R, t, [&](const float4& p0, const float4&, int64_t s) {
       const uint32_t bb = __float_as_uint(p0.w);
       const int b0 = bb & 1023, b1 = (bb >> 10) & 1023, b2 = bb >> 20;
       const int n0 = b2, n1 = (b2 + 1) & (RES - 1);
@@ -1433,7 +1433,7 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
           part[((MODE == PI_FWD ? 0 : c * 4) + slot) * np + s] = qv;
         }
       }
-    }
+    });
   }
 }
 
