@@ -363,16 +363,21 @@ int psr_chamfer_workspace_bytes(int64_t nx, int64_t ny, size_t* bytes);
 
 /* Bidirectional L2 Chamfer distance (main Eq. 5) between x ([nx][3]) and y
  * ([ny][3]): nn_x[i] / d_x[i] = nearest y and its squared distance, nn_y /
- * d_y the same from y to x (brute force in FP32; equal distances go to the
- * lower index), and, when loss is not NULL, *loss = mean(d_x) + mean(d_y)
- * (one double, device memory, FP64 sums). */
+ * d_y the same from y to x, and, when loss is not NULL, *loss = mean(d_x) +
+ * mean(d_y) (one double, device memory, FP64 sums in a fixed order). The
+ * result is the brute-force one (squared FP32 distances, equal distances go
+ * to the lower index): both clouds are sorted into spatial tiles and a tile
+ * is skipped only when its box is farther than a distance already found.
+ * A point with a NaN coordinate is nobody's neighbour; a query with one gets
+ * index -1 and distance +inf. */
 int psr_chamfer(psr_ctx* ctx, const float* x, int64_t nx, const float* y, int64_t ny, int32_t* nn_x, float* d_x,
                 int32_t* nn_y, float* d_y, double* loss, void* workspace, size_t workspace_bytes,
                 hipStream_t stream);
 
 /* grad_x = dL/dx of the Chamfer loss from its nearest-neighbour indices:
  * 2 (x_i - y_nn_x[i]) / nx, plus 2 (x_i - y_j) / ny for every j with
- * nn_y[j] = i (float atomics for the second term). */
+ * nn_y[j] = i (float atomics for the second term). A sample without a
+ * neighbour (nn_x[i] = -1) gets NaN; a target point without one adds nothing. */
 int psr_chamfer_backward(psr_ctx* ctx, const float* x, int64_t nx, const float* y, int64_t ny, const int32_t* nn_x,
                          const int32_t* nn_y, float* grad_x, hipStream_t stream);
 

@@ -15,11 +15,20 @@ struct SampleLayout {
 };
 SampleLayout sample_layout(int64_t nfaces);
 
+// Chamfer workspace: per cloud (x, y) the cell counts / offsets of the
+// counting sort, the sorted points (x, y, z, original index bits) and the
+// bounding box of every tile of kNnTile sorted points.
+constexpr int kNnTile = 64;  // sorted points per tile
+// 2^b cells per axis (Morton-ordered): about four or more points per cell
+inline int nn_cell_bits(int64_t nx, int64_t ny) {
+  const int64_t n = nx > ny ? nx : ny;
+  return n <= 32768 ? 4 : (n <= 262144 ? 5 : 6);
+}
 struct NnLayout {
-  int chunks;
-  size_t pd, pi, total;  // per chunk and query: nearest distance and index
+  int cell_bits;
+  size_t cnt, srt_x, srt_y, box_x, box_y, part, total;  // part: each query group's FP64 share of the loss
 };
-NnLayout nn_layout(int64_t nq, int64_t nr);
+NnLayout nn_layout(int64_t nx, int64_t ny);
 size_t chamfer_ws(int64_t nx, int64_t ny);
 
 struct CompLayout {

@@ -7,10 +7,9 @@
 // Sampling: FP64 face areas, an FP64 inclusive scan (block sums, their scan,
 // block-local scans), then per sample a binary search of u0 * total and the
 // barycentric weights (1 - sqrt(u1), sqrt(u1) (1 - u2), sqrt(u1) u2).
-// Chamfer: brute-force nearest neighbours, every query against a chunk of the
-// reference cloud staged through LDS per workgroup (enough chunks that the
-// grid fills the chip), the chunks' minima reduced in index order (equal
-// distances go to the lower index); FP64 sums for the loss.
+// Chamfer: exact nearest neighbours over spatially sorted tiles whose boxes
+// let whole tiles be skipped (the brute-force result: equal distances go to
+// the lower index); FP64 sums for the loss.
 // Components: label propagation over the triangles (atomic minimum) with
 // pointer jumping until no label changes, FP64 areas per label, and the
 // label with the greatest area (ties: the lowest label).
@@ -153,73 +152,471 @@ __global__ __launch_bounds__(256) void k_sample_bwd(const int32_t* __restrict__ 
   }
 }
 
-// nearest reference point of each query within one chunk of the references
-__global__ __launch_bounds__(256) void k_nn_chunk(const float* __restrict__ q, int64_t nq, const float* __restrict__ r,
-                                                  int64_t nr, int64_t chunk, float* __restrict__ pd,
-                                                  int32_t* __restrict__ pi) {
-  __shared__ float4 tile[256];
-  const int64_t qi = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t c = blockIdx.y;
-  const int64_t r0 = c * chunk, r1 = r0 + chunk < nr ? r0 + chunk : nr;
-  float qx = 0.0f, qy = 0.0f, qz = 0.0f;
-  if (qi < nq) {
-    qx = q[3 * qi];
-    qy = q[3 * qi + 1];
-    qz = q[3 * qi + 2];
+// ---------------------------------------------------------------------------
+// Nearest neighbours for the Chamfer loss: an exact search that skips whole
+// tiles of the reference cloud. Both clouds are counting-sorted into
+// Morton-ordered cells of a grid over [0,1)^3 (16^3 to 64^3 cells by cloud
+// size; points outside fall into the border cells), cut into tiles of
+// kNnTile sorted points, and each tile gets its bounding box. A query group
+// (kNnTile sorted queries) visits the reference tiles nearest its own box
+// first and stops where every remaining box is farther than each query's
+// best so far; a tile is skipped when no query's point-to-box bound reaches
+// its best. The bounds use the same FP32
+// operations as the distances (monotone rounding), so a skipped point is
+// strictly farther than a distance already found: the result is the
+// brute-force one, the squared FP32 distance minimised with equal distances
+// going to the lower reference index.
+// ---------------------------------------------------------------------------
+
+// squared length, evaluated the same way for distances and for bounds
+__device__ __forceinline__ float nn_d2(float ax, float ay, float az) {
+  return __fmaf_rn(az, az, __fmaf_rn(ay, ay, ax * ax));
+}
+
+__device__ __forceinline__ int nn_cell_coord(float v, int cb) {
+  const int top = (1 << cb) - 1;
+  const float c = v * (float)(1 << cb);
+  if (!(c >= 0.0f)) return 0;  // also NaN
+  return c >= (float)top ? top : (int)c;
+}
+
+__device__ __forceinline__ uint32_t nn_spread(uint32_t v) {  // up to 8 bits -> every third bit
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// Morton index of the point's cell in the 2^cb per axis grid
+__device__ __forceinline__ int nn_key(float x, float y, float z, int cb) {
+  return (int)(nn_spread(nn_cell_coord(x, cb)) | (nn_spread(nn_cell_coord(y, cb)) << 1) |
+               (nn_spread(nn_cell_coord(z, cb)) << 2));
+}
+
+__global__ __launch_bounds__(256) void k_nn_zero(int* __restrict__ cnt, int n) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) cnt[i] = 0;
+}
+
+// cell counts of both clouds (x: points [0, nx), y: the next ny)
+__global__ __launch_bounds__(256) void k_nn_count(const float* __restrict__ x, int64_t nx,
+                                                  const float* __restrict__ y, int64_t ny, int* __restrict__ cnt,
+                                                  int cb) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nx + ny) return;
+  const bool isy = i >= nx;
+  const float* p = isy ? y + 3 * (i - nx) : x + 3 * i;
+  atomicAdd(&cnt[(isy ? 1 << (3 * cb) : 0) + nn_key(p[0], p[1], p[2], cb)], 1);
+}
+
+// exclusive scan of one cloud's nc cell counts in place (workgroup = cloud;
+// each thread owns nc / 1024 consecutive counts)
+__global__ __launch_bounds__(1024) void k_nn_scan(int* __restrict__ cnt, int nc) {
+  __shared__ int wsum[16];
+  int4* c = reinterpret_cast<int4*>(cnt + (int64_t)blockIdx.x * nc);
+  const int per4 = nc / 4096;
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  int s = 0;
+  for (int k = 0; k < per4; ++k) {
+    const int4 a = c[t * per4 + k];
+    s += a.x + a.y + a.z + a.w;
   }
-  float best = __int_as_float(0x7f800000);
-  int32_t bi = -1;
-  for (int64_t t0 = r0; t0 < r1; t0 += 256) {
-    const int64_t j = t0 + threadIdx.x;
+  int inc = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += u;
+  }
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  int run = inc - s;
+  for (int v = 0; v < wid; ++v) run += wsum[v];
+  for (int k = 0; k < per4; ++k) {
+    const int4 a = c[t * per4 + k];
+    int4 o;
+    o.x = run;
+    o.y = o.x + a.x;
+    o.z = o.y + a.y;
+    o.w = o.z + a.z;
+    run = o.w + a.w;
+    c[t * per4 + k] = o;
+  }
+}
+
+// points into cell order: (x, y, z, original index bits); the offsets end as
+// the cells' ends
+__global__ __launch_bounds__(256) void k_nn_scatter(const float* __restrict__ x, int64_t nx,
+                                                    const float* __restrict__ y, int64_t ny, int* __restrict__ cnt,
+                                                    float4* __restrict__ sx, float4* __restrict__ sy, int cb) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nx + ny) return;
+  const bool isy = i >= nx;
+  const int64_t k = isy ? i - nx : i;
+  const float* p = (isy ? y : x) + 3 * k;
+  const float a = p[0], b = p[1], c = p[2];
+  const int pos = atomicAdd(&cnt[(isy ? 1 << (3 * cb) : 0) + nn_key(a, b, c, cb)], 1);
+  (isy ? sy : sx)[pos] = make_float4(a, b, c, __int_as_float((int)k));
+}
+
+// bounding box of each tile (one wavefront per tile; NaN coordinates ignored)
+__global__ __launch_bounds__(64) void k_nn_box(const float4* __restrict__ sx, int64_t nx,
+                                               const float4* __restrict__ sy, int64_t ny, int64_t tx,
+                                               float4* __restrict__ bx, float4* __restrict__ by) {
+  const int64_t tb = blockIdx.x;
+  const bool isy = tb >= tx;
+  const int64_t t = isy ? tb - tx : tb, n = isy ? ny : nx;
+  const int64_t i = t * kNnTile + threadIdx.x;
+  const float inf = __int_as_float(0x7f800000);
+  float lo[3] = {inf, inf, inf}, hi[3] = {-inf, -inf, -inf};
+  if (i < n) {
+    const float4 p = (isy ? sy : sx)[i];
+    lo[0] = hi[0] = p.x;
+    lo[1] = hi[1] = p.y;
+    lo[2] = hi[2] = p.z;
+    if (p.x != p.x) lo[0] = inf, hi[0] = -inf;
+    if (p.y != p.y) lo[1] = inf, hi[1] = -inf;
+    if (p.z != p.z) lo[2] = inf, hi[2] = -inf;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], __shfl_xor(lo[a], d, 64));
+      hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], d, 64));
+    }
+  }
+  if (threadIdx.x == 0) {
+    float4* b = (isy ? by : bx) + 2 * t;
+    b[0] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+    b[1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+  }
+}
+
+// float <-> int keys whose integer order is the float order (NaN excluded)
+__device__ __forceinline__ int nn_ord(float f) {
+  const int i = __float_as_int(f);
+  return i >= 0 ? i : i ^ 0x7fffffff;
+}
+__device__ __forceinline__ float nn_unord(int k) { return __int_as_float(k >= 0 ? k : k ^ 0x7fffffff); }
+
+constexpr int kNnSmallBits = 4;                           // 16^3 cells
+constexpr int kNnSmallCells = 1 << (3 * kNnSmallBits);
+constexpr int kNnSmallTiles = 512;                        // clouds of up to 32768 points
+
+// Small clouds (up to kNnSmallTiles tiles): the whole counting sort of one
+// cloud in one workgroup (counts, scan and ranks in LDS), the tile boxes from
+// LDS minima / maxima during the scatter; writes the sorted points, the
+// cells' ends and the boxes, as the separate kernels do for larger clouds.
+__global__ __launch_bounds__(1024) void k_nn_sort_small(const float* __restrict__ x, int64_t nx,
+                                                        const float* __restrict__ y, int64_t ny,
+                                                        int* __restrict__ cnt, float4* __restrict__ sx,
+                                                        float4* __restrict__ sy, float4* __restrict__ bx,
+                                                        float4* __restrict__ by) {
+  __shared__ int hist[kNnSmallCells];
+  __shared__ int bmin[3][kNnSmallTiles], bmax[3][kNnSmallTiles];
+  __shared__ int wsum[16];
+  const bool isy = blockIdx.x == 1;
+  const float* p = isy ? y : x;
+  const int n = (int)(isy ? ny : nx);
+  float4* srt = isy ? sy : sx;
+  float4* box = isy ? by : bx;
+  int* ends = cnt + (isy ? kNnSmallCells : 0);
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const int nt = (n + kNnTile - 1) / kNnTile;
+  for (int k = t; k < kNnSmallCells; k += 1024) hist[k] = 0;
+  for (int k = t; k < kNnSmallTiles; k += 1024) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      bmin[a][k] = 0x7fffffff;
+      bmax[a][k] = (int)0x80000000;
+    }
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int i = t; i < n; i += 1024) atomicAdd(&hist[nn_key(p[3 * i], p[3 * i + 1], p[3 * i + 2], kNnSmallBits)], 1);
+  __syncthreads();
+  {
+    constexpr int PER = kNnSmallCells / 1024;
+    int v[PER], s = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      v[k] = hist[t * PER + k];
+      s += v[k];
+    }
+    int inc = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int u = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += u;
+    }
+    if (lane == 63) wsum[wid] = inc;
     __syncthreads();
-    tile[threadIdx.x] = j < r1 ? make_float4(r[3 * j], r[3 * j + 1], r[3 * j + 2], 0.0f) : make_float4(0, 0, 0, 0);
-    __syncthreads();
-    const int n = r1 - t0 < 256 ? (int)(r1 - t0) : 256;
-    for (int k = 0; k < n; ++k) {
-      const float4 p = tile[k];
-      const float dx = qx - p.x, dy = qy - p.y, dz = qz - p.z;
-      const float d = dx * dx + dy * dy + dz * dz;
-      if (d < best) {
-        best = d;
-        bi = (int32_t)(t0 + k);
+    int run = inc - s;
+    for (int u = 0; u < wid; ++u) run += wsum[u];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      hist[t * PER + k] = run;
+      run += v[k];
+    }
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int i = t; i < n; i += 1024) {
+    const float a = p[3 * i], b = p[3 * i + 1], c = p[3 * i + 2];
+    const int pos = atomicAdd(&hist[nn_key(a, b, c, kNnSmallBits)], 1);
+    srt[pos] = make_float4(a, b, c, __int_as_float(i));
+    const int tl = pos / kNnTile;
+    const float v[3] = {a, b, c};
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      if (v[e] == v[e]) {
+        atomicMin(&bmin[e][tl], nn_ord(v[e]));
+        atomicMax(&bmax[e][tl], nn_ord(v[e]));
       }
     }
   }
-  if (qi < nq) {
-    pd[c * nq + qi] = best;
-    pi[c * nq + qi] = bi;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_nn_reduce(const float* __restrict__ pd, const int32_t* __restrict__ pi,
-                                                   int64_t nq, int nchunks, int32_t* __restrict__ nn,
-                                                   float* __restrict__ dist) {
-  const int64_t qi = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (qi >= nq) return;
-  float best = pd[qi];
-  int32_t bi = pi[qi];
-  for (int c = 1; c < nchunks; ++c) {
-    const float d = pd[(int64_t)c * nq + qi];
-    if (d < best) {
-      best = d;
-      bi = pi[(int64_t)c * nq + qi];
+  __syncthreads();
+  for (int k = t; k < kNnSmallCells; k += 1024) ends[k] = hist[k];
+  const float inf = __int_as_float(0x7f800000);
+  for (int k = t; k < nt; k += 1024) {
+    float lo[3], hi[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      lo[e] = bmin[e][k] == 0x7fffffff ? inf : nn_unord(bmin[e][k]);
+      hi[e] = bmax[e][k] == (int)0x80000000 ? -inf : nn_unord(bmax[e][k]);
     }
+    box[2 * k] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+    box[2 * k + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
   }
-  nn[qi] = bi;
-  dist[qi] = best;
 }
 
-// loss = mean(d_x) + mean(d_y), FP64 sums in a fixed order (one workgroup)
-__global__ __launch_bounds__(256) void k_chamfer_loss(const float* __restrict__ dx, int64_t nx,
-                                                      const float* __restrict__ dy, int64_t ny,
-                                                      double* __restrict__ loss) {
-  __shared__ double sh[256];
-  double a = 0.0, b = 0.0;
-  for (int64_t i = threadIdx.x; i < nx; i += 256) a += dx[i];
-  for (int64_t i = threadIdx.x; i < ny; i += 256) b += dy[i];
-  double tot;
-  block_excl_scan(a / (double)nx + b / (double)ny, sh, tot);
-  if (threadIdx.x == 0) *loss = tot;
+// squared distance bound from point q to box [lo, hi]
+__device__ __forceinline__ float nn_box_d2(float qx, float qy, float qz, const float4& lo, const float4& hi) {
+  return nn_d2(fmaxf(fmaxf(lo.x - qx, qx - hi.x), 0.0f), fmaxf(fmaxf(lo.y - qy, qy - hi.y), 0.0f),
+               fmaxf(fmaxf(lo.z - qz, qz - hi.z), 0.0f));
+}
+
+// squared distance bound between boxes [al, ah] and [bl, bh]
+__device__ __forceinline__ float nn_boxbox_d2(const float3& al, const float3& ah, const float4& bl, const float4& bh) {
+  return nn_d2(fmaxf(fmaxf(bl.x - ah.x, al.x - bh.x), 0.0f), fmaxf(fmaxf(bl.y - ah.y, al.y - bh.y), 0.0f),
+               fmaxf(fmaxf(bl.z - ah.z, al.z - bh.z), 0.0f));
+}
+
+// orders this wavefront's LDS writes before its own later reads (and the
+// reverse) without a workgroup barrier: the four wavefronts of a group take
+// different numbers of tiles
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct NnSide {
+  const float4* q;   // sorted queries
+  int64_t nq;
+  const float4* r;   // sorted references
+  const float4* box; // reference tile boxes (lo, hi)
+  const int* rend;   // reference cell ends
+  int64_t nr;
+  int32_t* nn;
+  float* dist;
+};
+
+constexpr int kNnWaves = 4;
+constexpr int kNnCand = 512;  // tiles tested per pass: the capacity of the candidate list
+
+// One group of kNnTile sorted queries per workgroup, four wavefronts holding
+// the same queries; groups [0, gx) search y from x, the rest x from y.
+// 1. Each wavefront scans one of the four tiles around the reference cell of
+//    the group's first query; the largest best distance of the group then
+//    bounds every neighbour.
+// 2. The tiles whose box lies within that bound of the group's box are listed
+//    in LDS with their boxes and sorted by the box-to-box bound (bitonic).
+// 3. The wavefronts take the sorted tiles in turn (the next one's points
+//    prefetched) and stop at the first whose box bound exceeds every lane's
+//    best; a tile is passed over when no lane's point-to-box bound reaches
+//    that lane's best. A lane's best is the lowest distance any wavefront has
+//    reached for it (published in LDS after every tile).
+// 4. The four results per query are merged (lower distance, then lower
+//    index), and the group's share of the mean distance is written to part.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_nn_query(
+    const NnSide A, const NnSide Bs, int64_t gx, int cb, double* __restrict__ part) {
+  __shared__ float4 stg[kNnWaves][kNnTile];
+  __shared__ float shb[kNnWaves][kNnTile];
+  __shared__ int sidx[kNnWaves][kNnTile];
+  __shared__ float4 cbox[kNnCand][2];  // lo (w: box bound), hi (w: tile - c0)
+  __shared__ unsigned long long ckey[kNnCand];  // (box bound, slot in cbox)
+  __shared__ int ncand;
+  const bool second = blockIdx.x >= gx;
+  const NnSide S = second ? Bs : A;
+  const int64_t g = second ? blockIdx.x - gx : blockIdx.x;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const float inf = __int_as_float(0x7f800000), nan = __int_as_float(0x7fc00000);
+  const int64_t gi = g * kNnTile + lane;
+  const bool active = gi < S.nq;
+  const float4 q = active ? S.q[gi] : make_float4(nan, nan, nan, 0.0f);
+  // the group's box (NaN coordinates ignored)
+  float3 ql = make_float3(inf, inf, inf), qh = make_float3(-inf, -inf, -inf);
+  if (q.x == q.x) ql.x = qh.x = q.x;
+  if (q.y == q.y) ql.y = qh.y = q.y;
+  if (q.z == q.z) ql.z = qh.z = q.z;
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    ql.x = fminf(ql.x, __shfl_xor(ql.x, d, 64));
+    ql.y = fminf(ql.y, __shfl_xor(ql.y, d, 64));
+    ql.z = fminf(ql.z, __shfl_xor(ql.z, d, 64));
+    qh.x = fmaxf(qh.x, __shfl_xor(qh.x, d, 64));
+    qh.y = fmaxf(qh.y, __shfl_xor(qh.y, d, 64));
+    qh.z = fmaxf(qh.z, __shfl_xor(qh.z, d, 64));
+  }
+  const int64_t ntr = (S.nr + kNnTile - 1) / kNnTile;
+  const int key = __builtin_amdgcn_readfirstlane(nn_key(q.x, q.y, q.z, cb));
+  int64_t t0 = S.rend[key] / kNnTile;
+  t0 = t0 > ntr - 1 ? ntr - 1 : t0;
+  int64_t s0 = t0 - 1 > ntr - kNnWaves ? ntr - kNnWaves : t0 - 1;
+  s0 = s0 < 0 ? 0 : s0;
+  const int64_t s1 = s0 + kNnWaves - 1;  // the start tiles [s0, s1] (fewer when ntr < 4)
+  float best = inf;
+  int bi = 0x7fffffff;
+  auto publish = [&]() { __hip_atomic_store(&shb[w][lane], best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
+  // the lowest distance reached for this query by any wavefront so far
+  auto reached = [&]() {
+    float u = best;
+#pragma unroll
+    for (int v = 0; v < kNnWaves; ++v)
+      u = fminf(u, __hip_atomic_load(&shb[v][lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+    return u;
+  };
+  auto group_bound = [&](float u) {
+    float b = active ? u : 0.0f;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) b = fmaxf(b, __shfl_xor(b, d, 64));
+    return b;
+  };
+  // this lane's point of tile t; a short last tile is padded with points at
+  // infinity and the largest index, which never win
+  auto tile_point = [&](int64_t t) {
+    const int64_t i = t * kNnTile + lane;
+    return i < S.nr ? S.r[i] : make_float4(inf, inf, inf, __int_as_float(0x7fffffff));
+  };
+  auto scan_tile = [&](const float4& p) {
+    wave_sync();
+    stg[w][lane] = p;
+    wave_sync();
+    // sixteen LDS reads in flight per batch
+#pragma unroll 1
+    for (int k0 = 0; k0 < kNnTile; k0 += 16) {
+      float4 e[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) e[u] = stg[w][k0 + u];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const float d = nn_d2(e[u].x - q.x, e[u].y - q.y, e[u].z - q.z);
+        const int j = __float_as_int(e[u].w);
+        const bool better = (d < best) | ((d == best) & (j < bi));
+        best = better ? d : best;
+        bi = better ? j : bi;
+      }
+    }
+    publish();
+  };
+  scan_tile(tile_point(s0 + w < ntr ? s0 + w : ntr - 1));
+  __syncthreads();
+  float bound = group_bound(reached());
+  for (int64_t c0 = 0; c0 < ntr; c0 += kNnCand) {
+    if (threadIdx.x == 0) ncand = 0;
+    __syncthreads();
+    const int64_t c1 = c0 + kNnCand < ntr ? c0 + kNnCand : ntr;
+    for (int64_t t = c0 + threadIdx.x; t < c1; t += 256) {
+      if (t >= s0 && t <= s1) continue;
+      const float4 lo = S.box[2 * t], hi = S.box[2 * t + 1];
+      const float lb = nn_boxbox_d2(ql, qh, lo, hi);
+      if (lb <= bound) {
+        const int k = atomicAdd(&ncand, 1);
+        cbox[k][0] = make_float4(lo.x, lo.y, lo.z, lb);
+        cbox[k][1] = make_float4(hi.x, hi.y, hi.z, __int_as_float((int)(t - c0)));
+        ckey[k] = ((unsigned long long)__float_as_uint(lb) << 32) | (uint32_t)k;
+      }
+    }
+    __syncthreads();
+    const int nc = ncand;
+    int np2 = 1;
+    while (np2 < nc) np2 <<= 1;
+    for (int i = nc + threadIdx.x; i < np2; i += 256) ckey[i] = ~0ull;
+    __syncthreads();
+    // ascending bitonic sort of the keys: the nearest boxes first
+    for (int k = 2; k <= np2; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = threadIdx.x; i < np2; i += 256) {
+          const int l = i ^ j;
+          if (l > i) {
+            const unsigned long long a = ckey[i], b = ckey[l];
+            if ((a > b) == ((i & k) == 0)) {
+              ckey[i] = b;
+              ckey[l] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    auto slot = [&](int i) { return (int)(ckey[i] & 0xffffffffu); };
+    float4 pf = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (w < nc) pf = tile_point(c0 + __float_as_int(cbox[slot(w)][1].w));
+    for (int i = w; i < nc; i += kNnWaves) {
+      const int k = slot(i);
+      const float4 lo = cbox[k][0], hi = cbox[k][1];
+      const float4 cur = pf;
+      if (i + kNnWaves < nc) pf = tile_point(c0 + __float_as_int(cbox[slot(i + kNnWaves)][1].w));
+      const float ub = reached();
+      if (lo.w > group_bound(ub)) break;  // every later box is farther
+      const bool need = active && nn_box_d2(q.x, q.y, q.z, lo, hi) <= ub;
+      if (__any(need)) scan_tile(cur);
+    }
+    __syncthreads();
+    bound = group_bound(reached());
+  }
+  sidx[w][lane] = bi;
+  publish();
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int v = 1; v < kNnWaves; ++v) {
+      const float d = shb[v][lane];
+      const int j = sidx[v][lane];
+      const bool better = (d < best) | ((d == best) & (j < bi));
+      best = better ? d : best;
+      bi = better ? j : bi;
+    }
+    if (active) {
+      const int qi = __float_as_int(q.w);
+      S.nn[qi] = bi == 0x7fffffff ? -1 : bi;
+      S.dist[qi] = best;
+    }
+    double m = active ? (double)best / (double)S.nq : 0.0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m += __shfl_xor(m, d, 64);
+    if (lane == 0) part[blockIdx.x] = m;
+  }
+}
+
+// loss = mean(d_x) + mean(d_y) from the query groups' FP64 shares, summed in
+// group order (one workgroup: strided per-thread sums, then a fixed tree)
+__global__ __launch_bounds__(1024) void k_chamfer_loss(const double* __restrict__ part, int64_t ng,
+                                                       double* __restrict__ loss) {
+  __shared__ double sh[16];
+  const int t = threadIdx.x;
+  double v = 0.0;
+#pragma unroll 4
+  for (int64_t i = t; i < ng; i += 1024) v += part[i];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  if ((t & 63) == 0) sh[t >> 6] = v;
+  __syncthreads();
+  if (t == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < 16; ++w) tot += sh[w];
+    *loss = tot;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_chamfer_bwd_x(const float* __restrict__ x, int64_t nx,
@@ -229,6 +626,11 @@ __global__ __launch_bounds__(256) void k_chamfer_bwd_x(const float* __restrict__
   if (i >= nx) return;
   const int64_t j = nnx[i];
   const float s = 2.0f / (float)nx;
+  if (j < 0) {  // no neighbour: the query holds NaN
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[3 * i + d] = __int_as_float(0x7fc00000);
+    return;
+  }
 #pragma unroll
   for (int d = 0; d < 3; ++d) g[3 * i + d] = s * (x[3 * i + d] - y[3 * j + d]);
 }
@@ -239,6 +641,7 @@ __global__ __launch_bounds__(256) void k_chamfer_bwd_y(const float* __restrict__
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= ny) return;
   const int64_t i = nny[j];
+  if (i < 0) return;  // no neighbour: the target point holds NaN
   const float s = 2.0f / (float)ny;
 #pragma unroll
   for (int d = 0; d < 3; ++d) atomicAdd(&g[3 * i + d], s * (x[3 * i + d] - y[3 * j + d]));
@@ -356,50 +759,49 @@ int run_sample_backward(const int32_t* f, int64_t nv, const int32_t* face, const
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
-// chunks of the reference cloud per query block: enough workgroups to fill the chip
-static int nn_chunks(int64_t nq, int64_t nr) {
-  const int64_t qb = (nq + 255) / 256;
-  int64_t c = (2048 + qb - 1) / qb;
-  const int64_t maxc = (nr + 255) / 256;
-  if (c > maxc) c = maxc;
-  if (c < 1) c = 1;
-  return (int)c;
-}
-
-NnLayout nn_layout(int64_t nq, int64_t nr) {
+NnLayout nn_layout(int64_t nx, int64_t ny) {
   NnLayout L;
-  const int64_t c = nn_chunks(nq, nr);
-  L.chunks = (int)c;
-  L.pd = 0;
-  L.pi = align(c * nq * 4);
-  L.total = L.pi + align(c * nq * 4);
+  const int64_t tx = (nx + kNnTile - 1) / kNnTile, ty = (ny + kNnTile - 1) / kNnTile;
+  L.cell_bits = nn_cell_bits(nx, ny);
+  L.cnt = 0;
+  L.srt_x = align(2 * ((int64_t)1 << (3 * L.cell_bits)) * 4);
+  L.srt_y = L.srt_x + align(nx * 16);
+  L.box_x = L.srt_y + align(ny * 16);
+  L.box_y = L.box_x + align(tx * 32);
+  L.part = L.box_y + align(ty * 32);
+  L.total = L.part + align((tx + ty) * 8);
   return L;
 }
 
-static int run_nn(const float* q, int64_t nq, const float* r, int64_t nr, int32_t* nn, float* dist, void* ws,
-                  hipStream_t s) {
-  const NnLayout L = nn_layout(nq, nr);
-  float* pd = reinterpret_cast<float*>(static_cast<char*>(ws) + L.pd);
-  int32_t* pi = reinterpret_cast<int32_t*>(static_cast<char*>(ws) + L.pi);
-  int64_t chunk = (nr + L.chunks - 1) / L.chunks;
-  chunk = (chunk + 255) / 256 * 256;
-  const int nchunks = (int)((nr + chunk - 1) / chunk);
-  hipLaunchKernelGGL(k_nn_chunk, dim3(nb256(nq), nchunks), dim3(256), 0, s, q, nq, r, nr, chunk, pd, pi);
-  hipLaunchKernelGGL(k_nn_reduce, dim3(nb256(nq)), dim3(256), 0, s, pd, pi, nq, nchunks, nn, dist);
-  return hipGetLastError() == hipSuccess ? 0 : -4;
-}
-
-size_t chamfer_ws(int64_t nx, int64_t ny) {
-  const size_t a = nn_layout(nx, ny).total, b = nn_layout(ny, nx).total;
-  return a > b ? a : b;
-}
+size_t chamfer_ws(int64_t nx, int64_t ny) { return nn_layout(nx, ny).total; }
 
 int run_chamfer(const float* x, int64_t nx, const float* y, int64_t ny, int32_t* nnx, float* dx, int32_t* nny,
                 float* dy, double* loss, void* ws, hipStream_t s) {
-  int rc = run_nn(x, nx, y, ny, nnx, dx, ws, s);  // the two directions reuse the workspace in stream order
-  rc |= run_nn(y, ny, x, nx, nny, dy, ws, s);
-  if (loss) hipLaunchKernelGGL(k_chamfer_loss, dim3(1), dim3(256), 0, s, dx, nx, dy, ny, loss);
-  return rc || hipGetLastError() != hipSuccess ? -4 : 0;
+  const NnLayout L = nn_layout(nx, ny);
+  char* b = static_cast<char*>(ws);
+  int* cnt = reinterpret_cast<int*>(b + L.cnt);
+  float4* sx = reinterpret_cast<float4*>(b + L.srt_x);
+  float4* sy = reinterpret_cast<float4*>(b + L.srt_y);
+  float4* bx = reinterpret_cast<float4*>(b + L.box_x);
+  float4* by = reinterpret_cast<float4*>(b + L.box_y);
+  const int64_t tx = (nx + kNnTile - 1) / kNnTile, ty = (ny + kNnTile - 1) / kNnTile;
+  const int cb = L.cell_bits, nc = 1 << (3 * cb);
+  static_assert(kNnSmallTiles * kNnTile == 32768, "the small-cloud sort covers the clouds given 16^3 cells");
+  if (cb == kNnSmallBits && tx <= kNnSmallTiles && ty <= kNnSmallTiles) {
+    hipLaunchKernelGGL(k_nn_sort_small, dim3(2), dim3(1024), 0, s, x, nx, y, ny, cnt, sx, sy, bx, by);
+  } else {
+    hipLaunchKernelGGL(k_nn_zero, dim3(64), dim3(256), 0, s, cnt, 2 * nc);
+    hipLaunchKernelGGL(k_nn_count, dim3(nb256(nx + ny)), dim3(256), 0, s, x, nx, y, ny, cnt, cb);
+    hipLaunchKernelGGL(k_nn_scan, dim3(2), dim3(1024), 0, s, cnt, nc);
+    hipLaunchKernelGGL(k_nn_scatter, dim3(nb256(nx + ny)), dim3(256), 0, s, x, nx, y, ny, cnt, sx, sy, cb);
+    hipLaunchKernelGGL(k_nn_box, dim3(tx + ty), dim3(64), 0, s, sx, nx, sy, ny, tx, bx, by);
+  }
+  const NnSide A{sx, nx, sy, by, cnt + nc, ny, nnx, dx};  // samples x against the target y
+  const NnSide B{sy, ny, sx, bx, cnt, nx, nny, dy};       // and back
+  double* part = reinterpret_cast<double*>(b + L.part);
+  hipLaunchKernelGGL(k_nn_query, dim3(tx + ty), dim3(256), 0, s, A, B, tx, cb, part);
+  if (loss) hipLaunchKernelGGL(k_chamfer_loss, dim3(1), dim3(1024), 0, s, part, tx + ty, loss);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 
 int run_chamfer_backward(const float* x, int64_t nx, const float* y, int64_t ny, const int32_t* nnx,

@@ -72,7 +72,7 @@ def test_sampling_backward_matches_oracle(dev):
     assert e <= 1e-5
 
 
-@pytest.mark.parametrize("nx,ny", [(20000, 20000), (5000, 30000), (257, 1)])
+@pytest.mark.parametrize("nx,ny", [(20000, 20000), (5000, 30000), (257, 1), (40000, 3000)])
 def test_chamfer_matches_oracle(dev, nx, ny):
     from paper_2106_03452_amd import optimize as O
     announce(f"chamfer {nx} x {ny} vs oracle")
@@ -93,6 +93,61 @@ def test_chamfer_matches_oracle(dev, nx, ny):
     e = l2_rel(host(X.grad), ref["grad"])
     print(f"chamfer {nx}x{ny}: loss {float(loss):.6e} (ref {ref['loss']:.6e}), grad e={e:.2e}")
     assert e <= 1e-5
+
+
+def _check_nn(d_g, nn_g, a, b, d_r):
+    assert np.abs(d_g - d_r).max() <= 1e-5 * max(d_r.max(), 1e-12)
+    assert nn_g.min() >= 0 and nn_g.max() < len(b)
+    dd = ((a.astype(np.float64) - b.astype(np.float64)[nn_g]) ** 2).sum(1)
+    assert np.abs(dd - d_r).max() <= 1e-5 * max(d_r.max(), 1e-12)
+
+
+@pytest.mark.parametrize("case", ["surfaces", "outside_and_clustered", "one_cell", "duplicates", "single_query"])
+def test_chamfer_structured_clouds_match_oracle(dev, case):
+    """The search skips tiles of the sorted reference cloud by their boxes; it
+    must still return the brute-force neighbours on clouds that stress that:
+    two surfaces apart (the loop's clouds), points outside [0,1)^3 and a dense
+    cluster (cells spanning many tiles), every point in one cell, exact
+    duplicates (equal distances: the lower index), a lone query."""
+    from paper_2106_03452_amd import optimize as O
+    announce(f"chamfer {case} vs oracle")
+    rng = np.random.default_rng(3)
+    if case == "surfaces":
+        x = S.tiny_case(7, 64, 9000, kind="sphere").points
+        y = S.tiny_case(11, 64, 12000, kind="torus").points
+    elif case == "outside_and_clustered":
+        x = rng.uniform(-0.5, 1.5, (7000, 3)).astype(np.float32)
+        y = np.concatenate([rng.normal(0.5, 0.03, (9000, 3)), rng.uniform(0, 1, (1000, 3))]).astype(np.float32)
+    elif case == "one_cell":
+        x = rng.uniform(0.40, 0.401, (3000, 3)).astype(np.float32)
+        y = rng.uniform(0.40, 0.401, (5000, 3)).astype(np.float32)
+    elif case == "duplicates":
+        x = rng.random((6000, 3)).astype(np.float32)
+        y0 = rng.random((4000, 3)).astype(np.float32)
+        y = np.concatenate([y0, y0])
+    else:
+        x = rng.random((1, 3)).astype(np.float32)
+        y = rng.random((20000, 3)).astype(np.float32)
+    loss, nnx, dx, nny, dy = O.chamfer_raw(to_dev(x, dev), to_dev(y, dev))
+    ref = oopt.chamfer(x, y)
+    nnx_g, nny_g = host(nnx).astype(np.int64), host(nny).astype(np.int64)
+    _check_nn(host(dx), nnx_g, x, y, ref["d_x"])
+    _check_nn(host(dy), nny_g, y, x, ref["d_y"])
+    if case == "duplicates":
+        # the copies of a target point are at exactly equal distances
+        assert nnx_g.max() < len(y0)
+        assert np.array_equal(nny_g[:len(y0)], nny_g[len(y0):])
+    # the same neighbours as the oracle wherever its nearest distance is not
+    # tied within the tolerance by another point
+    for nn_g, nn_r, a, b in ((nnx_g, ref["nn_x"], x, y), (nny_g, ref["nn_y"], y, x)):
+        diff = np.nonzero(nn_g != nn_r)[0]
+        for i in diff[:200]:
+            da = ((a[i].astype(np.float64) - b[nn_g[i]]) ** 2).sum()
+            db = ((a[i].astype(np.float64) - b[nn_r[i]]) ** 2).sum()
+            assert abs(da - db) <= 1e-5 * max(db, 1e-12), (i, da, db)
+    assert abs(float(loss) - ref["loss"]) <= 1e-6 * ref["loss"]
+    print(f"chamfer {case}: loss {float(loss):.6e} (ref {ref['loss']:.6e}), "
+          f"{int((nnx_g != ref['nn_x']).sum() + (nny_g != ref['nn_y']).sum())} tied neighbours differ")
 
 
 def test_components_match_oracle(dev):
