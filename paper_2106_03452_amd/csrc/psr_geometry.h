@@ -51,6 +51,15 @@ __host__ __device__ constexpr int tile_rows(int res) {
               (res >= PSR_PLANE_SPLIT_MIN && res <= 128) ? res / 2 : res);
 }
 __host__ __device__ constexpr int rows_block(int res) { return tile_rows(res) * plan_TPL(res / 2); }
+// Workgroup size of the row passes. Up to 32 a row tile is the whole plane
+// and its transforms take one thread per row (res threads); the workgroup
+// is widened to 256 threads for the loops over the plane's points and
+// samples, the threads beyond the rows transforming scratch rows.
+__host__ __device__ constexpr int rows_wg(int res) { return res <= 32 ? 256 : rows_block(res); }
+// LDS rows of a row-pass workgroup: the tile's rows plus the scratch rows
+__host__ __device__ constexpr int rows_lds(int res) {
+  return rows_wg(res) / plan_TPL(res / 2) > tile_rows(res) ? rows_wg(res) / plan_TPL(res / 2) : tile_rows(res);
+}
 __host__ __device__ constexpr int row_tiles(int res) { return res / tile_rows(res); }
 __host__ __device__ constexpr int num_bins(int res) { return 2 * res * row_tiles(res); }
 

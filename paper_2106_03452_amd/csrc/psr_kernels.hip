@@ -496,10 +496,10 @@ __device__ __forceinline__ void b_splat_r2c(const PointRec* __restrict__ sorted,
                                                               const cf* __restrict__ tw, cf* __restrict__ out,
                                                               float* __restrict__ vout, const float* __restrict__ chi_in,
                                                               double2* __restrict__ bpart_w, int bid) {
-  constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_block(RES);
+  constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_wg(RES);
   constexpr int TPL = plan_TPL(M), E = plan_E(M), LS = row_ls(M);
   constexpr int64_t N3 = (int64_t)RES * RES * RES;
-  __shared__ __align__(16) cf rows[TR * LS];
+  __shared__ __align__(16) cf rows[rows_lds(RES) * LS];
   __shared__ cf stw[M];      // FFT table of length M
   __shared__ cf rtw[M + 1];  // W_RES^k, k in [0, M], for the r2c post-processing
   float* rf = reinterpret_cast<float*>(rows);
@@ -916,9 +916,9 @@ __device__ __forceinline__ void b_c2r_gather(const cf* __restrict__ in,
                                                                const int* __restrict__ off,
                                                                float4* __restrict__ part, int64_t np,
                                                                const cf* __restrict__ tw, int bid) {
-  constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_block(RES);
+  constexpr int M = RES / 2, H = M + 1, TR = tile_rows(RES), NT = row_tiles(RES), BR = rows_wg(RES);
   constexpr int TPL = plan_TPL(M), E = plan_E(M), LS = row_ls(M);
-  __shared__ __align__(16) cf rows[TR * LS];
+  __shared__ __align__(16) cf rows[rows_lds(RES) * LS];
   __shared__ cf stw[M];      // FFT table of length M
   __shared__ cf rtw[M + 1];  // W_RES^k, k in [0, M], for the c2r pre-processing
   const float* rf = reinterpret_cast<const float*>(rows);
@@ -1782,7 +1782,7 @@ __global__ __launch_bounds__(256) void k_scan_scatter(const Batch<MAXJ> B) {
 }
 
 template <int RES, int MODE, int MAXJ>
-__global__ __launch_bounds__(rows_block(RES)) void k_splat_r2c(const Batch<MAXJ> B) {
+__global__ __launch_bounds__(rows_wg(RES)) void k_splat_r2c(const Batch<MAXJ> B) {
   PSR_JOB(RES);
   if constexpr (MODE == MODE_BWDH || MODE == MODE_BWDA) { PSR_BWD_GUARD(RES); }
   const float* gin = MODE == MODE_BWDH || MODE == MODE_BWDA ? J.dchi : J.aux_in;
@@ -1819,7 +1819,7 @@ __global__ __launch_bounds__(cols_block(RES)) void k_axis1_inv(const Batch<MAXJ>
 }
 
 template <int RES, int MODE, int MAXJ>
-__global__ __launch_bounds__(rows_block(RES)) void k_c2r_gather(const Batch<MAXJ> B) {
+__global__ __launch_bounds__(rows_wg(RES)) void k_c2r_gather(const Batch<MAXJ> B) {
   PSR_JOB(RES);
   if constexpr (MODE == MODE_BWD) { PSR_BWD_GUARD(RES); }
   float* out = MODE == MODE_DBG ? J.aux_out : J.chi;
@@ -1915,7 +1915,7 @@ struct Grid {
   static constexpr int cols = H * (RES / tile_cols(RES));  // column-pass workgroups per channel
   static constexpr int j0s = H * (RES / tile_j0(RES));     // workgroups of the fused j0 passes
   static constexpr int BJ = j0_block(RES);
-  static constexpr int BR = rows_block(RES), BC = cols_block(RES);
+  static constexpr int BR = rows_wg(RES), BC = cols_block(RES);
   static constexpr int64_t N3 = (int64_t)RES * RES * RES;
   static constexpr int init_blocks = nblk_c(num_bins(RES), 256) > 64 ? 64 : nblk_c(num_bins(RES), 256);
   static constexpr int norm_blocks = nblk_c(N3 / 4, 256) > 1024 ? 1024 : nblk_c(N3 / 4, 256);
