@@ -657,7 +657,7 @@ def training_leg(dev, torch, batch=8, steps=10, warmup=3, res=128):
     c = torch.from_numpy(np.stack(c_in)).to(dev)
     torch.manual_seed(0)
     model = learn.OffsetNormalNet(k=7).to(dev)
-    opt = torch.optim.Adam(model.parameters(), lr=1e-4)
+    opt = torch.optim.Adam(model.parameters(), lr=1e-4, fused=True)
     for _ in range(warmup):
         learn.train_step(model, opt, c, gt, res)
     torch.cuda.synchronize()

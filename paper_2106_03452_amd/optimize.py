@@ -205,7 +205,7 @@ def optimise(target: torch.Tensor, schedule=PAPER_SCHEDULE, npoints: int = 20000
             p, n = resample(mm.verts, mm.faces, mm.normals, npoints, gen)
         p = p.clone().requires_grad_(True)
         n = n.clone().requires_grad_(True)
-        opt = torch.optim.Adam([p, n], lr=lr * decay ** li)
+        opt = torch.optim.Adam([p, n], lr=lr * decay ** li, fused=True)  # one kernel per step
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for it in range(lev.iters):
@@ -216,7 +216,7 @@ def optimise(target: torch.Tensor, schedule=PAPER_SCHEDULE, npoints: int = 20000
                     pn, nn = resample(mm.verts, mm.faces, mm.normals, npoints, gen)
                 p = pn.clone().requires_grad_(True)
                 n = nn.clone().requires_grad_(True)
-                opt = torch.optim.Adam([p, n], lr=lr * decay ** li)
+                opt = torch.optim.Adam([p, n], lr=lr * decay ** li, fused=True)  # one kernel per step
             u = torch.rand((nsamples, 3), generator=gen, device=dev, dtype=torch.float32)
             opt.zero_grad(set_to_none=True)
             loss, (verts, faces) = step_loss(p, n, target, lev.res, lev.sigma, u)

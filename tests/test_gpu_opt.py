@@ -150,6 +150,33 @@ def test_chamfer_structured_clouds_match_oracle(dev, case):
           f"{int((nnx_g != ref['nn_x']).sum() + (nny_g != ref['nn_y']).sum())} tied neighbours differ")
 
 
+def test_chamfer_nan_point_has_no_neighbour(dev):
+    """A sample with a NaN coordinate is nobody's nearest neighbour and has
+    none itself (index -1, distance +inf, NaN gradient); the other samples'
+    neighbours and gradients are those of the cloud without it."""
+    from paper_2106_03452_amd import optimize as O
+    announce("chamfer with a NaN sample")
+    rng = np.random.default_rng(9)
+    x = rng.random((3000, 3)).astype(np.float32)
+    y = rng.random((2000, 3)).astype(np.float32)
+    xn = x.copy()
+    xn[17, 1] = np.nan
+    loss, nnx, dx, nny, dy = O.chamfer_raw(to_dev(xn, dev), to_dev(y, dev))
+    nnx, dx, nny, dy = host(nnx), host(dx), host(nny), host(dy)
+    assert nnx[17] == -1 and np.isinf(dx[17]) and np.isinf(float(loss))
+    keep = np.arange(len(x)) != 17
+    ref = oopt.chamfer(x[keep], y)
+    remap = np.nonzero(keep)[0]
+    _check_nn(dx[keep], nnx[keep].astype(np.int64), x[keep], y, ref["d_x"])
+    _check_nn(dy, nny.astype(np.int64), y, xn, ref["d_y"])
+    assert (nny != 17).all()
+    print(f"NaN sample: {int((remap[ref['nn_y']] != nny).sum())} tied neighbours differ")
+    X = to_dev(xn, dev).requires_grad_(True)
+    O.ChamferFunction.apply(X, to_dev(y, dev)).backward()
+    g = host(X.grad)
+    assert np.isnan(g[17]).all() and np.isfinite(g[keep]).all()
+
+
 def test_components_match_oracle(dev):
     from paper_2106_03452_amd import optimize as O
     announce("mesh components vs oracle")
