@@ -696,11 +696,12 @@ def main():
                     help="requests of the compact serving leg of the default run (levels 1.0 and 1.5 x lambda_seq)")
     ap.add_argument("--no-serve", action="store_true", help="skip the compact serving leg")
     ap.add_argument("--no-loops", action="store_true", help="skip the optimisation-loop and training-step legs")
-    ap.add_argument("--workload", choices=["c3", "c2", "c4", "mc", "slab", "sweep"], default="c3",
+    ap.add_argument("--workload", choices=["c3", "c2", "c4", "mc", "slab", "sweep", "opt"], default="c3",
                     help="profiling runs: c3 = the headline line (default); c2 = only the 128^3 fwd+bwd steps; "
                          "c4 = only the 64-shape batch; mc = only Marching Cubes of the 256^3 solve; "
                          "slab = only the 1024^3 slab forward; sweep = grid sizes 64-512 x 1e4-1e6 points "
-                         "and the 1024^3 slab forward at 2, 8, 32 slabs")
+                         "and the 1024^3 slab forward at 2, 8, 32 slabs; opt = only the optimisation loop "
+                         "(--steps iterations per grid size)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB five times (scale reference for HBM counters)")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -752,6 +753,9 @@ def main():
             print(json.dumps({"workload": "slab", **slab_leg(dev, torch, args.steps, args.warmup)}), flush=True)
         elif args.workload == "c4":
             print(json.dumps({"workload": "c4", **batch_c4(dev, torch, args.steps, args.warmup)}), flush=True)
+        elif args.workload == "opt":
+            print(json.dumps({"workload": "opt", **optimisation_leg(dev, torch, iters=max(2, args.steps))}),
+                  flush=True)
         else:
             b3 = prepare(S.config_c3(), dev, torch, F)
             print(json.dumps({"workload": "mc", **marching_cubes_leg(dev, torch, b3["chi"], args.steps)}), flush=True)

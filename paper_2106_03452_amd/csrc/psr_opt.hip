@@ -681,12 +681,24 @@ __global__ __launch_bounds__(256) void k_fill0d(double* __restrict__ x, int64_t 
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) x[i] = 0.0;
 }
 
+// Area per label. A mesh is mostly one or a few components, so the 64
+// triangles of a wavefront usually share a label: they are then summed by
+// shuffles and added with one atomic instead of 64 on the same address.
 __global__ __launch_bounds__(256) void k_comp_area(const int32_t* __restrict__ f, int64_t nf,
                                                    const int32_t* __restrict__ lab, const double* __restrict__ area,
                                                    double* __restrict__ carea) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= nf) return;
-  atomicAdd(&carea[lab[f[3 * i]]], area[i]);
+  const bool ok = i < nf;
+  const int l = ok ? lab[f[3 * i]] : -1;
+  double a = ok ? area[i] : 0.0;
+  const int l0 = __builtin_amdgcn_readfirstlane(l);  // lane 0: the wavefront's first triangle
+  if (__all(l == l0 || !ok)) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) a += __shfl_xor(a, d, 64);
+    if ((threadIdx.x & 63) == 0 && l0 >= 0) atomicAdd(&carea[l0], a);
+  } else if (ok) {
+    atomicAdd(&carea[l], a);
+  }
 }
 
 // the label of greatest area (ties: the lowest label), one workgroup
