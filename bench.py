@@ -619,18 +619,23 @@ def optimisation_leg(dev, torch, iters=40, npoints=20000):
     torus, 20k points): ms per iteration (solve, Marching Cubes, sampling,
     Chamfer, every backward and the Adam step) at each grid size of the
     paper's schedule, a resampling from the largest component included every
-    `iters // 2` iterations, and the whole schedule's time from them."""
+    `iters // 2` iterations, and the whole schedule's time from them; each
+    iteration one psr_opt_step call, and beside it the same loop through the
+    autograd Functions and PyTorch's Adam."""
     import psr_synth as S
     from paper_2106_03452_amd import optimize as O
     target = torch.from_numpy(S.tiny_case(8, 256, npoints, kind="torus").points).to(dev)
     out = {"workload": f"{npoints}-point torus target, {npoints} source points and samples, "
                        f"{iters} iterations per grid size", "ms_per_iter": {}}
+    out["ms_per_iter_autograd"] = {}
     for lev in O.PAPER_SCHEDULE:
-        # a short untimed run first: first-use costs (tables, allocator) stay out
-        O.optimise(target, [O.Level(lev.res, lev.sigma, 5)], npoints=npoints, resample_every=100, log_every=0)
-        r = O.optimise(target, [O.Level(lev.res, lev.sigma, iters)], npoints=npoints, resample_every=iters // 2,
-                       log_every=0)
-        out["ms_per_iter"][str(lev.res)] = round(r.ms_per_iter[lev.res], 3)
+        for native, key in ((True, "ms_per_iter"), (False, "ms_per_iter_autograd")):
+            # a short untimed run first: first-use costs (tables, allocator) stay out
+            O.optimise(target, [O.Level(lev.res, lev.sigma, 5)], npoints=npoints, resample_every=100, log_every=0,
+                       native=native)
+            r = O.optimise(target, [O.Level(lev.res, lev.sigma, iters)], npoints=npoints,
+                           resample_every=iters // 2, log_every=0, native=native)
+            out[key][str(lev.res)] = round(r.ms_per_iter[lev.res], 3)
     full = sum(out["ms_per_iter"][str(l.res)] * l.iters for l in O.PAPER_SCHEDULE) / 1e3
     out["schedule_s"] = round(full, 2)
     out["schedule"] = "32^3 x1000, 64^3 x1000, 128^3 x1000, 256^3 x200 (sigma 2, 2, 3, 3)"

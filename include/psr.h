@@ -394,6 +394,36 @@ int psr_mesh_components(psr_ctx* ctx, const float* verts, int64_t nverts, const 
                         int32_t* labels, float* largest, void* workspace, size_t workspace_bytes,
                         hipStream_t stream);
 
+/* Bytes of the workspace of psr_opt_step (host only): the solve's workspace,
+ * saved state and grids, the Marching Cubes state and a mesh of at most vcap
+ * vertices and tcap triangles, the samples, the Chamfer buffers and every
+ * gradient. */
+int psr_opt_step_workspace_bytes(int res, int64_t npoints, int64_t ntarget, int64_t nsamples, int64_t vcap,
+                                 int64_t tcap, size_t* bytes);
+
+/* One iteration of the optimisation-based reconstruction (main Sec. 3.2,
+ * Eqs. 5-6), in one call instead of one per step: the solve of (points,
+ * normals) on the res^3 grid, Marching Cubes of chi = 0 (at most vcap
+ * vertices, tcap triangles), nsamples points sampled by area with the
+ * caller's uniform numbers u ([nsamples][3] in [0, 1)), the Chamfer loss to
+ * target ([ntarget][3]), the backward through the samples, the mesh and the
+ * solver's adjoint, and one Adam step with step count t >= 1 (learning rate
+ * lr, beta1, beta2, eps; first and second moments m_*, v_* of points and
+ * normals, [npoints][3] float32, updated in place) on the points, which are
+ * then wrapped into [0, 1) (the periodic domain), and on the normals.
+ * *loss (device double) receives the Chamfer loss; mesh_counts (host,
+ * int64_t[2], may be NULL) the mesh's vertices and triangles. The same
+ * kernels as the separate calls, in the same order. Synchronises the stream
+ * once, to read the mesh size. Returns PSR_ETOOBIG with points, normals and
+ * moments untouched when the mesh exceeds vcap or tcap (mesh_counts then
+ * holds the sizes needed), PSR_EDEGENERATE when the mesh is empty. Calls
+ * that overlap on one workspace race. */
+int psr_opt_step(psr_ctx* ctx, float* points, float* normals, int64_t npoints, float* m_points, float* v_points,
+                 float* m_normals, float* v_normals, int64_t t, float lr, float beta1, float beta2, float eps,
+                 const float* target, int64_t ntarget, const float* u, int64_t nsamples, int res, float sigma,
+                 int64_t vcap, int64_t tcap, double* loss, int64_t* mesh_counts, void* workspace,
+                 size_t workspace_bytes, hipStream_t stream);
+
 /* Test hook (host only): the case table the kernels use. ntri[256]: triangles
  * per sign pattern (bit k = corner k inside, corner k at offset (k&1,
  * (k>>1)&1, k>>2)); edges[256][15]: their local edge ids, edge 4a + u + 2v

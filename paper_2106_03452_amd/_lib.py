@@ -97,6 +97,9 @@ def _declare(L):
         "psr_chamfer_backward": ([vp, vp, i64, vp, i64, vp, vp, vp, vp], i32),
         "psr_mesh_components_workspace_bytes": ([i64, i64, P(sz)], i32),
         "psr_mesh_components": ([vp, vp, i64, vp, i64, vp, vp, vp, sz, vp], i32),
+        "psr_opt_step_workspace_bytes": ([i32, i64, i64, i64, i64, i64, P(sz)], i32),
+        "psr_opt_step": ([vp, vp, vp, i64, vp, vp, vp, vp, i64, f32, f32, f32, f32, vp, i64, vp, i64, i32, f32,
+                          i64, i64, vp, P(i64), vp, sz, vp], i32),
         "psr_ctx_stage_times": ([vp, P(f64), P(i64), i32], i32),
         "psr_ctx_reset_timers": ([vp], i32),
         "psr_stage_name": ([i32], ctypes.c_char_p),

@@ -651,6 +651,130 @@ int psr_mesh_components(psr_ctx* ctx, const float* verts, int64_t nverts, const 
   return rc == 0 ? PSR_OK : (rc == -5 ? PSR_ENOTREADY : PSR_EDEVICE);
 }
 
+namespace {
+
+// Workspace of psr_opt_step: every buffer of the iteration, 256-byte aligned.
+struct OptStepLayout {
+  size_t fws, saved, chi, dchi, mcs, verts, vnorm, edges, tris, sws, x, face, bary, cws, nnx, dx, nny, dy, gx, dv, dp,
+      dn, total;
+  size_t fws_bytes, sws_bytes, cws_bytes;
+};
+
+OptStepLayout opt_step_layout(int res, int64_t P, int64_t T, int64_t S, int64_t vcap, int64_t tcap) {
+  OptStepLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t& f, size_t bytes) {
+    f = o;
+    o += (bytes + 255) & ~(size_t)255;
+  };
+  const size_t r3 = (size_t)res * res * res;
+  size_t mcb = 0;
+  psr_mc_state_bytes(res, &mcb);
+  L.fws_bytes = psr::ws_layout(res, P).total;
+  L.sws_bytes = psr::opt::sample_layout(tcap).total;
+  L.cws_bytes = psr::opt::chamfer_ws(S, T);
+  take(L.fws, L.fws_bytes);
+  take(L.saved, psr::saved_layout(res, P).total);
+  take(L.chi, r3 * 4);
+  take(L.dchi, r3 * 4);
+  take(L.mcs, mcb);
+  take(L.verts, (size_t)vcap * 12);
+  take(L.vnorm, (size_t)vcap * 12);
+  take(L.edges, (size_t)vcap * 4);
+  take(L.tris, (size_t)tcap * 12);
+  take(L.sws, L.sws_bytes);
+  take(L.x, (size_t)S * 12);
+  take(L.face, (size_t)S * 4);
+  take(L.bary, (size_t)S * 12);
+  take(L.cws, L.cws_bytes);
+  take(L.nnx, (size_t)S * 4);
+  take(L.dx, (size_t)S * 4);
+  take(L.nny, (size_t)T * 4);
+  take(L.dy, (size_t)T * 4);
+  take(L.gx, (size_t)S * 12);
+  take(L.dv, (size_t)vcap * 12);
+  take(L.dp, (size_t)P * 12);
+  take(L.dn, (size_t)P * 12);
+  L.total = o;
+  return L;
+}
+
+bool opt_step_sizes_ok(int res, int64_t P, int64_t T, int64_t S, int64_t vcap, int64_t tcap) {
+  constexpr int64_t lim = (int64_t)1 << 31;
+  return valid_res(res) && valid_P(P) && T >= 1 && T < lim && S >= 1 && S < lim && vcap >= 1 && vcap < lim &&
+         tcap >= 1 && tcap < lim;
+}
+
+}  // namespace
+
+int psr_opt_step_workspace_bytes(int res, int64_t npoints, int64_t ntarget, int64_t nsamples, int64_t vcap,
+                                 int64_t tcap, size_t* bytes) {
+  if (!bytes || !opt_step_sizes_ok(res, npoints, ntarget, nsamples, vcap, tcap)) return PSR_EINVAL;
+  *bytes = opt_step_layout(res, npoints, ntarget, nsamples, vcap, tcap).total;
+  return PSR_OK;
+}
+
+int psr_opt_step(psr_ctx* ctx, float* points, float* normals, int64_t npoints, float* m_points, float* v_points,
+                 float* m_normals, float* v_normals, int64_t t, float lr, float beta1, float beta2, float eps,
+                 const float* target, int64_t ntarget, const float* u, int64_t nsamples, int res, float sigma,
+                 int64_t vcap, int64_t tcap, double* loss, int64_t* mesh_counts, void* workspace,
+                 size_t workspace_bytes, hipStream_t stream) {
+  if (!ctx || !points || !normals || !m_points || !v_points || !m_normals || !v_normals || !target || !u || !loss ||
+      !workspace)
+    return PSR_EINVAL;
+  if (!opt_step_sizes_ok(res, npoints, ntarget, nsamples, vcap, tcap) || t < 1) return PSR_EINVAL;
+  if (!(sigma >= 0.0f) || !std::isfinite(sigma) || !std::isfinite(lr) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+      !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) || !std::isfinite(eps))
+    return PSR_EINVAL;
+  if (!aligned(workspace, 256)) return PSR_EINVAL;
+  const OptStepLayout L = opt_step_layout(res, npoints, ntarget, nsamples, vcap, tcap);
+  if (workspace_bytes < L.total) return PSR_EINVAL;
+  char* b = static_cast<char*>(workspace);
+  auto f32 = [&](size_t o) { return reinterpret_cast<float*>(b + o); };
+  auto i32 = [&](size_t o) { return reinterpret_cast<int32_t*>(b + o); };
+  float* chi = f32(L.chi);
+  int rc = psr_forward(ctx, points, normals, npoints, res, sigma, chi, b + L.saved, b + L.fws, L.fws_bytes, stream);
+  if (rc != PSR_OK) return rc;
+  rc = psr_marching_cubes(ctx, chi, res, 0.0f, f32(L.verts), f32(L.vnorm), i32(L.edges), vcap, i32(L.tris), tcap,
+                          b + L.mcs, stream);
+  if (rc != PSR_OK) return rc;
+  int64_t nv = 0, nt = 0;
+  int st = PSR_OK;
+  rc = psr_mc_counts(b + L.mcs, stream, &nv, &nt, &st);
+  if (rc != PSR_OK) return rc;
+  if (mesh_counts) {
+    mesh_counts[0] = nv;
+    mesh_counts[1] = nt;
+  }
+  if (st != PSR_OK || nv > vcap || nt > tcap) return PSR_ETOOBIG;
+  if (nv == 0 || nt == 0) return PSR_EDEGENERATE;
+  // forward chain: samples of the mesh, Chamfer loss (main Eq. 5)
+  if ((rc = psr_mesh_sample(ctx, f32(L.verts), nullptr, nv, i32(L.tris), nt, nullptr, u, nsamples, f32(L.x), nullptr,
+                            i32(L.face), f32(L.bary), b + L.sws, L.sws_bytes, stream)) != PSR_OK)
+    return rc;
+  if ((rc = psr_chamfer(ctx, f32(L.x), nsamples, target, ntarget, i32(L.nnx), f32(L.dx), i32(L.nny), f32(L.dy), loss,
+                        b + L.cws, L.cws_bytes, stream)) != PSR_OK)
+    return rc;
+  // backward chain: samples -> vertices -> grid (main Eq. 6) -> points and normals
+  if ((rc = psr_chamfer_backward(ctx, f32(L.x), nsamples, target, ntarget, i32(L.nnx), i32(L.nny), f32(L.gx),
+                                 stream)) != PSR_OK)
+    return rc;
+  if ((rc = psr_mesh_sample_backward(ctx, i32(L.tris), nv, i32(L.face), f32(L.bary), f32(L.gx), nsamples, f32(L.dv),
+                                     stream)) != PSR_OK)
+    return rc;
+  if ((rc = psr_marching_cubes_backward(ctx, chi, res, 0.0f, b + L.mcs, f32(L.vnorm), f32(L.dv), nv, f32(L.dchi),
+                                        stream)) != PSR_OK)
+    return rc;
+  if ((rc = psr_backward(ctx, npoints, res, sigma, chi, b + L.saved, f32(L.dchi), f32(L.dp), f32(L.dn), b + L.fws,
+                         L.fws_bytes, stream)) != PSR_OK)
+    return rc;
+  DeviceGuard g(ctx->device);
+  rc = psr::opt::run_adam(points, m_points, v_points, f32(L.dp), 3 * npoints, t, lr, beta1, beta2, eps, true, stream);
+  rc |= psr::opt::run_adam(normals, m_normals, v_normals, f32(L.dn), 3 * npoints, t, lr, beta1, beta2, eps, false,
+                           stream);
+  return rc ? PSR_EDEVICE : PSR_OK;
+}
+
 int psr_mc_case_table(int8_t* ntri, int8_t* edges) {
   if (!ntri && !edges) return PSR_EINVAL;
   psr::mc::case_table(ntri, edges);

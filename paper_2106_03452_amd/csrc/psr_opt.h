@@ -44,6 +44,9 @@ int run_chamfer(const float* x, int64_t nx, const float* y, int64_t ny, int32_t*
                 float* dy, double* loss, void* ws, hipStream_t s);
 int run_chamfer_backward(const float* x, int64_t nx, const float* y, int64_t ny, const int32_t* nnx,
                          const int32_t* nny, float* g, hipStream_t s);
+// Adam on n values (moments m, v in place), then p -= floor(p) when wrap
+int run_adam(float* p, float* m, float* v, const float* g, int64_t n, int64_t t, float lr, float b1, float b2,
+             float eps, bool wrap, hipStream_t s);
 int run_components(const float* v, int64_t nv, const int32_t* f, int64_t nf, int32_t* lab, float* w, void* ws,
                    hipStream_t s, int max_iters);
 

@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include "psr_opt.h"
 
 namespace psr {
@@ -820,6 +822,33 @@ int run_chamfer_backward(const float* x, int64_t nx, const float* y, int64_t ny,
                          const int32_t* nny, float* g, hipStream_t s) {
   hipLaunchKernelGGL(k_chamfer_bwd_x, dim3(nb256(nx)), dim3(256), 0, s, x, nx, y, nnx, g);
   hipLaunchKernelGGL(k_chamfer_bwd_y, dim3(nb256(ny)), dim3(256), 0, s, x, y, ny, nny, g);
+  return hipGetLastError() == hipSuccess ? 0 : -4;
+}
+
+// Adam (Kingma and Ba): m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
+// p <- p - (lr / (1 - b1^t)) m / (sqrt(v) / sqrt(1 - b2^t) + eps); the bias
+// corrections come from the host in double precision.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                                              const float* __restrict__ g, int64_t n, float b1, float b2,
+                                              float step, float inv_sqrt_bc2, float eps, int wrap) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  float pi = p[i] - step * mi / (sqrtf(vi) * inv_sqrt_bc2 + eps);
+  if (wrap) pi -= floorf(pi);
+  p[i] = pi;
+}
+
+int run_adam(float* p, float* m, float* v, const float* g, int64_t n, int64_t t, float lr, float b1, float b2,
+             float eps, bool wrap, hipStream_t s) {
+  const double bc1 = 1.0 - std::pow((double)b1, (double)t), bc2 = 1.0 - std::pow((double)b2, (double)t);
+  if (n > 0)
+    hipLaunchKernelGGL(k_adam, dim3(nb256(n)), dim3(256), 0, s, p, m, v, g, n, b1, b2, (float)(lr / bc1),
+                       (float)(1.0 / std::sqrt(bc2)), eps, wrap ? 1 : 0);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

@@ -13,8 +13,9 @@ iterations; Adam, learning rate 2e-3 decayed by 0.7 at every new grid size).
 
 Every step (solve, Marching Cubes, sampling, Chamfer, components and all
 backwards) runs in ``libpsr.so``; this module draws the random numbers with
-PyTorch's generator, marshals buffers, and drives the loop with PyTorch's
-Adam.
+PyTorch's generator and marshals buffers. By default an iteration is one
+library call (``psr_opt_step``, Adam included); the same loop also runs
+through autograd Functions around the separate calls with PyTorch's Adam.
 """
 from __future__ import annotations
 
@@ -185,11 +186,59 @@ def step_loss(points, normals, target, res, sigma, u):
     return ChamferFunction.apply(x, target), (verts, faces)
 
 
+class NativeStep:
+    """One iteration in one library call (``psr_opt_step``): solve, Marching
+    Cubes, sampling, Chamfer loss, the backward chain and the Adam step run
+    in libpsr, so the host issues one call per iteration instead of
+    PyTorch's per-operation dispatch and autograd bookkeeping. Holds the
+    workspace, sized for a mesh cap that grows when a mesh exceeds it."""
+
+    def __init__(self, dev, npoints: int, ntarget: int, nsamples: int, res: int):
+        self.dev, self.P, self.T, self.S, self.res = dev, int(npoints), int(ntarget), int(nsamples), int(res)
+        self.vcap, self.tcap = max(4096, 8 * res * res), max(8192, 16 * res * res)
+        self.counts = (ctypes.c_int64 * 2)()
+        self.loss = torch.zeros((), dtype=torch.float64, device=dev)
+        self._alloc()
+
+    def _alloc(self):
+        L = _lib.lib()
+        nbytes = _size(L.psr_opt_step_workspace_bytes, self.res, self.P, self.T, self.S, self.vcap, self.tcap)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.dev)
+
+    def __call__(self, p, n, moments, t: int, lr: float, target, u, sigma: float,
+                 betas=(0.9, 0.999), eps: float = 1e-8) -> torch.Tensor:
+        """Update p, n and moments = (m_p, v_p, m_n, v_n) in place; returns the
+        Chamfer loss (0-d float64 device tensor, valid until the next call)."""
+        L = _lib.lib()
+        mp, vp, mn, vn = moments
+        for _ in range(3):
+            rc = L.psr_opt_step(_ctx(self.dev).handle, _p(p), _p(n), self.P, _p(mp), _p(vp), _p(mn), _p(vn), int(t),
+                                float(lr), float(betas[0]), float(betas[1]), float(eps), _p(target), self.T, _p(u),
+                                self.S, self.res, float(sigma), self.vcap, self.tcap, _p(self.loss), self.counts,
+                                _p(self.ws), ctypes.c_size_t(self.ws.numel()), _st(self.dev))
+            if rc == _lib.PSR_ETOOBIG:  # nothing was updated: grow the mesh cap and run the step again
+                self.vcap = max(self.vcap, int(self.counts[0]))
+                self.tcap = max(self.tcap, int(self.counts[1]))
+                self._alloc()
+                continue
+            _lib.check(rc, "psr_opt_step")
+            return self.loss
+        raise RuntimeError("psr_opt_step: mesh cap did not settle")
+
+
 def optimise(target: torch.Tensor, schedule=PAPER_SCHEDULE, npoints: int = 20000, nsamples: int | None = None,
              lr: float = 2e-3, decay: float = 0.7, resample_every: int = 200, seed: int = 0,
-             init_radius: float = 0.3, log_every: int = 50) -> Result:
+             init_radius: float = 0.3, log_every: int = 50, native: bool = True) -> Result:
     """Fit an oriented point cloud to `target` ([T, 3] float32 CUDA points in
-    [0, 1)^3) by the coarse-to-fine schedule; returns the final cloud and mesh."""
+    [0, 1)^3) by the coarse-to-fine schedule; returns the final cloud and mesh.
+
+    native: each iteration is one ``psr_opt_step`` call (NativeStep; the
+    returned mesh is that of the final cloud); else the same steps through
+    the autograd Functions and PyTorch's Adam (the returned mesh is the last
+    iteration's)."""
+    if native:
+        return _optimise_native(target, schedule, npoints, nsamples, lr, decay, resample_every, seed, init_radius,
+                                log_every)
     dev = target.device
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
@@ -229,3 +278,45 @@ def optimise(target: torch.Tensor, schedule=PAPER_SCHEDULE, npoints: int = 20000
         torch.cuda.synchronize()
         ms[lev.res] = (time.perf_counter() - t0) / max(1, lev.iters) * 1e3
     return Result(p.detach(), n.detach(), verts.detach(), faces, res_hist, ms)
+
+
+def _optimise_native(target, schedule, npoints, nsamples, lr, decay, resample_every, seed, init_radius, log_every):
+    dev = target.device
+    target = target.contiguous()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    nsamples = nsamples or int(target.shape[0])
+    p, n = sphere_cloud(npoints, init_radius, gen, dev)
+    res_hist, ms = [], {}
+    for li, lev in enumerate(schedule):
+        if li > 0:
+            # sample the coarse mesh to start the finer grid
+            chi = F.solve(p, n, schedule[li - 1].res, schedule[li - 1].sigma)
+            mm = M.marching_cubes(chi)
+            p, n = resample(mm.verts, mm.faces, mm.normals, npoints, gen)
+        p, n = p.detach().clone().contiguous(), n.detach().clone().contiguous()
+        step = NativeStep(dev, npoints, int(target.shape[0]), nsamples, lev.res)
+        moments = [torch.zeros_like(p), torch.zeros_like(p), torch.zeros_like(n), torch.zeros_like(n)]
+        t = 0
+        lr_l = lr * decay ** li
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it in range(lev.iters):
+            if it > 0 and it % resample_every == 0:
+                chi = F.solve(p, n, lev.res, lev.sigma)
+                mm = M.marching_cubes(chi)
+                pn, nn = resample(mm.verts, mm.faces, mm.normals, npoints, gen)
+                p, n = pn.contiguous(), nn.contiguous()
+                for m in moments:
+                    m.zero_()
+                t = 0  # a fresh optimiser for the resampled cloud
+            u = torch.rand((nsamples, 3), generator=gen, device=dev, dtype=torch.float32)
+            t += 1
+            loss = step(p, n, moments, t, lr_l, target, u, lev.sigma)
+            if log_every and (it % log_every == 0 or it == lev.iters - 1):
+                res_hist.append((li, it, lev.res, float(loss)))
+        torch.cuda.synchronize()
+        ms[lev.res] = (time.perf_counter() - t0) / max(1, lev.iters) * 1e3
+    chi = F.solve(p, n, schedule[-1].res, schedule[-1].sigma)
+    mm = M.marching_cubes(chi)
+    return Result(p, n, mm.verts, mm.faces, res_hist, ms)

@@ -87,6 +87,23 @@ def test_null_arguments_rejected_without_device_work(L):
     assert L.psr_slab_debug_spectral(None, None, 64, 2.0, 4, None, None, 0, None) == _lib.PSR_EINVAL
 
 
+def test_opt_step_size_query_and_argument_checks(L):
+    out = ctypes.c_size_t(0)
+    assert L.psr_opt_step_workspace_bytes(32, 20000, 20000, 20000, 8192, 16384, ctypes.byref(out)) == _lib.PSR_OK
+    small = out.value
+    assert small > 0 and small % 256 == 0
+    assert L.psr_opt_step_workspace_bytes(64, 20000, 20000, 20000, 8192, 16384, ctypes.byref(out)) == _lib.PSR_OK
+    assert out.value > small  # the grids grow with res
+    for args in ((33, 10, 10, 10, 10, 10), (32, 0, 10, 10, 10, 10), (32, 10, 0, 10, 10, 10),
+                 (32, 10, 10, 0, 10, 10), (32, 10, 10, 10, 0, 10), (32, 10, 10, 10, 10, 0),
+                 (32, 10, 1 << 31, 10, 10, 10)):
+        assert L.psr_opt_step_workspace_bytes(*args, ctypes.byref(out)) == _lib.PSR_EINVAL
+    assert L.psr_opt_step_workspace_bytes(32, 10, 10, 10, 10, 10, None) == _lib.PSR_EINVAL
+    # argument checks fail before any device work
+    assert L.psr_opt_step(None, None, None, 10, None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None, 10, None,
+                          10, 32, 2.0, 100, 100, None, None, None, 0, None) == _lib.PSR_EINVAL
+
+
 def test_mc_case_table_matches_the_oracle(L):
     """The library builds its Marching Cubes table at compile time from the
     same face rule the oracle implements in Python: both must agree entry by

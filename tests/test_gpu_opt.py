@@ -218,13 +218,86 @@ def test_one_step_gradient_matches_oracle_chain(dev):
     assert e_l <= 1e-5 and e_c <= 1e-4 and e_n <= 1e-4
 
 
+def _adam_reference_step(p, n, target, res, sigma, u, lr, steps):
+    """The iteration through the autograd Functions and PyTorch's Adam."""
+    from paper_2106_03452_amd import optimize as O
+    p, n = p.clone().requires_grad_(True), n.clone().requires_grad_(True)
+    opt = torch.optim.Adam([p, n], lr=lr, fused=True)
+    losses = []
+    for k in range(steps):
+        opt.zero_grad(set_to_none=True)
+        loss, _ = O.step_loss(p, n, target, res, sigma, u[k])
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            p.remainder_(1.0)
+        losses.append(float(loss))
+    return p.detach(), n.detach(), losses
+
+
+def test_native_step_matches_the_autograd_step(dev):
+    """psr_opt_step runs the same kernels as the separate calls: the loss is
+    the same, and after three Adam steps the cloud agrees with PyTorch's Adam
+    on the autograd path (the float atomics of two backward stages reorder
+    the last bits of a few gradients; Adam's first steps move each value by
+    about lr times the sign of its gradient)."""
+    from paper_2106_03452_amd import optimize as O
+    announce("native optimisation step vs the autograd step, 32^3")
+    res, sigma, lr = 32, 2.0, 2e-3
+    sh = S.tiny_case(7, res, 3000, kind="sphere")
+    target = to_dev(S.tiny_case(11, res, 4000, kind="torus").points, dev)
+    p0, n0 = to_dev(sh.points, dev), to_dev(sh.normals, dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(3)
+    u = [torch.rand((2500, 3), generator=g, device=dev) for _ in range(3)]
+    pr, nr, losses = _adam_reference_step(p0, n0, target, res, sigma, u, lr, 3)
+    p, n = p0.clone(), n0.clone()
+    moments = [torch.zeros_like(p) for _ in range(4)]
+    step = O.NativeStep(dev, 3000, 4000, 2500, res)
+    for k in range(3):
+        loss = float(step(p, n, moments, k + 1, lr, target, u[k], sigma))
+        assert abs(loss - losses[k]) <= 1e-5 * losses[k], (k, loss, losses[k])
+    ep, en = float((p - pr).abs().max()), float((n - nr).abs().max())
+    print(f"native step: losses {losses}; max |dp| {ep:.2e}, max |dn| {en:.2e}")
+    assert ep <= 1e-5 and en <= 1e-5
+    assert bool(((p >= 0) & (p < 1)).all())
+
+
+def test_native_step_grows_its_mesh_cap(dev):
+    """A mesh larger than the workspace's cap leaves the cloud untouched
+    (PSR_ETOOBIG); the step then grows the cap and runs again, with the same
+    result as a step that had room from the start."""
+    from paper_2106_03452_amd import optimize as O
+    announce("native optimisation step with a small mesh cap")
+    res, sigma = 32, 2.0
+    sh = S.tiny_case(7, res, 3000, kind="sphere")
+    target = to_dev(S.tiny_case(11, res, 4000, kind="torus").points, dev)
+    u = torch.rand((2500, 3), generator=torch.Generator(device=dev).manual_seed(5), device=dev)
+    outs = []
+    for cap in (None, 16):
+        p, n = to_dev(sh.points, dev), to_dev(sh.normals, dev)
+        moments = [torch.zeros_like(p) for _ in range(4)]
+        step = O.NativeStep(dev, 3000, 4000, 2500, res)
+        if cap:
+            step.vcap = step.tcap = cap
+            step._alloc()
+        loss = float(step(p, n, moments, 1, 2e-3, target, u, sigma))
+        if cap:
+            assert step.vcap > cap and step.tcap > cap
+        outs.append((loss, p, n))
+    assert outs[0][0] == outs[1][0]
+    assert float((outs[0][1] - outs[1][1]).abs().max()) <= 1e-6
+    assert float((outs[0][2] - outs[1][2]).abs().max()) <= 1e-6
+
+
 def test_short_optimisation_lowers_chamfer(dev):
     from paper_2106_03452_amd import optimize as O
     announce("short coarse-to-fine optimisation")
     target = to_dev(S.tiny_case(8, 64, 5000, kind="torus").points, dev)
     sched = [O.Level(32, 2.0, 150), O.Level(64, 2.0, 100)]
-    r = O.optimise(target, sched, npoints=5000, resample_every=100, log_every=25, seed=1)
-    first, last = r.history[0][3], r.history[-1][3]
-    print(f"Chamfer {first:.3e} -> {last:.3e}; ms/iter {r.ms_per_iter}")
-    assert last < 0.3 * first
-    assert torch.isfinite(r.points).all() and r.faces.shape[0] > 0
+    for native in (True, False):
+        r = O.optimise(target, sched, npoints=5000, resample_every=100, log_every=25, seed=1, native=native)
+        first, last = r.history[0][3], r.history[-1][3]
+        print(f"native={native}: Chamfer {first:.3e} -> {last:.3e}; ms/iter {r.ms_per_iter}")
+        assert last < 0.3 * first
+        assert torch.isfinite(r.points).all() and r.faces.shape[0] > 0
