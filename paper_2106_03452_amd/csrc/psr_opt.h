@@ -26,7 +26,7 @@ inline int nn_cell_bits(int64_t nx, int64_t ny) {
 }
 struct NnLayout {
   int cell_bits;
-  size_t cnt, srt_x, srt_y, box_x, box_y, part, total;  // part: each query group's FP64 share of the loss
+  size_t cnt, srt_x, srt_y, box_x, box_y, total;
 };
 NnLayout nn_layout(int64_t nx, int64_t ny);
 size_t chamfer_ws(int64_t nx, int64_t ny);

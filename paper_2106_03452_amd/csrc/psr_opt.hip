@@ -439,9 +439,9 @@ constexpr int kNnCand = 512;  // tiles tested per pass: the capacity of the cand
 //    that lane's best. A lane's best is the lowest distance any wavefront has
 //    reached for it (published in LDS after every tile).
 // 4. The four results per query are merged (lower distance, then lower
-//    index), and the group's share of the mean distance is written to part.
+//    index).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_nn_query(
-    const NnSide A, const NnSide Bs, int64_t gx, int cb, double* __restrict__ part) {
+    const NnSide A, const NnSide Bs, int64_t gx, int cb) {
   __shared__ float4 stg[kNnWaves][kNnTile];
   __shared__ float shb[kNnWaves][kNnTile];
   __shared__ int sidx[kNnWaves][kNnTile];
@@ -594,22 +594,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
       S.nn[qi] = bi == 0x7fffffff ? -1 : bi;
       S.dist[qi] = best;
     }
-    double m = active ? (double)best / (double)S.nq : 0.0;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) m += __shfl_xor(m, d, 64);
-    if (lane == 0) part[blockIdx.x] = m;
   }
 }
 
-// loss = mean(d_x) + mean(d_y) from the query groups' FP64 shares, summed in
-// group order (one workgroup: strided per-thread sums, then a fixed tree)
-__global__ __launch_bounds__(1024) void k_chamfer_loss(const double* __restrict__ part, int64_t ng,
+// loss = mean(d_x) + mean(d_y), FP64 sums in a fixed order by point index
+// (one workgroup: strided per-thread sums, then a fixed tree), so the loss
+// does not depend on the order the search sorted the points in
+__global__ __launch_bounds__(1024) void k_chamfer_loss(const float* __restrict__ dx, int64_t nx,
+                                                       const float* __restrict__ dy, int64_t ny,
                                                        double* __restrict__ loss) {
   __shared__ double sh[16];
   const int t = threadIdx.x;
-  double v = 0.0;
-#pragma unroll 4
-  for (int64_t i = t; i < ng; i += 1024) v += part[i];
+  double a = 0.0, b = 0.0;
+#pragma unroll 8
+  for (int64_t i = t; i < nx; i += 1024) a += dx[i];
+#pragma unroll 8
+  for (int64_t i = t; i < ny; i += 1024) b += dy[i];
+  double v = a / (double)nx + b / (double)ny;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
   if ((t & 63) == 0) sh[t >> 6] = v;
@@ -782,8 +783,7 @@ NnLayout nn_layout(int64_t nx, int64_t ny) {
   L.srt_y = L.srt_x + align(nx * 16);
   L.box_x = L.srt_y + align(ny * 16);
   L.box_y = L.box_x + align(tx * 32);
-  L.part = L.box_y + align(ty * 32);
-  L.total = L.part + align((tx + ty) * 8);
+  L.total = L.box_y + align(ty * 32);
   return L;
 }
 
@@ -812,9 +812,8 @@ int run_chamfer(const float* x, int64_t nx, const float* y, int64_t ny, int32_t*
   }
   const NnSide A{sx, nx, sy, by, cnt + nc, ny, nnx, dx};  // samples x against the target y
   const NnSide B{sy, ny, sx, bx, cnt, nx, nny, dy};       // and back
-  double* part = reinterpret_cast<double*>(b + L.part);
-  hipLaunchKernelGGL(k_nn_query, dim3(tx + ty), dim3(256), 0, s, A, B, tx, cb, part);
-  if (loss) hipLaunchKernelGGL(k_chamfer_loss, dim3(1), dim3(1024), 0, s, part, tx + ty, loss);
+  hipLaunchKernelGGL(k_nn_query, dim3(tx + ty), dim3(256), 0, s, A, B, tx, cb);
+  if (loss) hipLaunchKernelGGL(k_chamfer_loss, dim3(1), dim3(1024), 0, s, dx, nx, dy, ny, loss);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

@@ -150,6 +150,21 @@ def test_chamfer_structured_clouds_match_oracle(dev, case):
           f"{int((nnx_g != ref['nn_x']).sum() + (nny_g != ref['nn_y']).sum())} tied neighbours differ")
 
 
+def test_chamfer_is_deterministic(dev):
+    """The search sorts the points with atomics, so their order within a
+    cell changes from call to call; the neighbours, the distances and the
+    loss must not."""
+    from paper_2106_03452_amd import optimize as O
+    announce("chamfer: repeated calls")
+    x = to_dev(S.tiny_case(7, 64, 20000, kind="sphere").points, dev)
+    y = to_dev(S.tiny_case(11, 64, 20000, kind="torus").points, dev)
+    first = [host(t) for t in O.chamfer_raw(x, y)]
+    for _ in range(4):
+        again = [host(t) for t in O.chamfer_raw(x, y)]
+        for a, b in zip(first, again):
+            assert np.array_equal(a, b)
+
+
 def test_chamfer_nan_point_has_no_neighbour(dev):
     """A sample with a NaN coordinate is nobody's nearest neighbour and has
     none itself (index -1, distance +inf, NaN gradient); the other samples'
