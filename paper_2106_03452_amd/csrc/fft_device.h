@@ -146,9 +146,26 @@ __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 // LDS ends its reads with a barrier; one that writes LDS ends with a barrier.
 // A first stage that writes LDS assumes the line is no longer being read.
 // `tw` is the table exp(-2 pi i e / L), e in [0, L).
-template <int L, int R, int NS, int DIR, bool IN_REG, bool OUT_REG>
+// WS (wavefront-synchronous): the TPL threads of a line are consecutive lanes
+// of one wavefront and only they touch the line, so the barriers order the
+// wavefront's own LDS accesses (in order in hardware; a fence keeps the
+// compiler from moving them) instead of the workgroup's. The caller then
+// synchronises the workgroup where other threads read or write the lines.
+__device__ __forceinline__ void fft_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+template <bool WS>
+__device__ __forceinline__ void fft_sync() {
+  if constexpr (WS) fft_wave_sync();
+  else __syncthreads();
+}
+
+template <int L, int R, int NS, int DIR, bool IN_REG, bool OUT_REG, bool WS = false>
 __device__ __forceinline__ void stage(cf* reg, cf* line, int lt, const cf* __restrict__ tw, int swz) {
   constexpr int E = plan_E(L), TPL = plan_TPL(L);
+  static_assert(!WS || 64 % TPL == 0, "a wavefront-synchronous line lies within one wavefront");
   constexpr int NB = E / R;
   constexpr int STRIDE = L / R;
   cf a[NB][R];
@@ -158,7 +175,7 @@ __device__ __forceinline__ void stage(cf* reg, cf* line, int lt, const cf* __res
 #pragma unroll
     for (int m = 0; m < R; ++m) a[u][m] = IN_REG ? reg[u + m * NB] : line[pidx(j + m * STRIDE) ^ swz];
   }
-  if constexpr (!IN_REG) __syncthreads();
+  if constexpr (!IN_REG) fft_sync<WS>();
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int j = lt + TPL * u;
@@ -179,39 +196,39 @@ __device__ __forceinline__ void stage(cf* reg, cf* line, int lt, const cf* __res
       else line[pidx(base + q * NS) ^ swz] = a[u][q];
     }
   }
-  if constexpr (!OUT_REG) __syncthreads();
+  if constexpr (!OUT_REG) fft_sync<WS>();
 }
 
 // Whole length-L transform. IN_REG / OUT_REG select where the first stage
 // reads and the last stage writes (canonical registers or the LDS line).
-template <int L, int DIR, bool IN_REG, bool OUT_REG>
+template <int L, int DIR, bool IN_REG, bool OUT_REG, bool WS = false>
 __device__ __forceinline__ void fft(cf* reg, cf* line, int lt, const cf* __restrict__ tw, int swz = 0) {
   if constexpr (L == 4) {
-    stage<4, 4, 1, DIR, IN_REG, OUT_REG>(reg, line, lt, tw, swz);
+    stage<4, 4, 1, DIR, IN_REG, OUT_REG, WS>(reg, line, lt, tw, swz);
   } else if constexpr (L == 8) {
-    stage<8, 8, 1, DIR, IN_REG, OUT_REG>(reg, line, lt, tw, swz);
+    stage<8, 8, 1, DIR, IN_REG, OUT_REG, WS>(reg, line, lt, tw, swz);
   } else if constexpr (L == 16) {
-    stage<16, 16, 1, DIR, IN_REG, OUT_REG>(reg, line, lt, tw, swz);
+    stage<16, 16, 1, DIR, IN_REG, OUT_REG, WS>(reg, line, lt, tw, swz);
   } else if constexpr (L == 32) {
-    stage<32, 8, 1, DIR, IN_REG, false>(reg, line, lt, tw, swz);
-    stage<32, 4, 8, DIR, false, OUT_REG>(reg, line, lt, tw, swz);
+    stage<32, 8, 1, DIR, IN_REG, false, WS>(reg, line, lt, tw, swz);
+    stage<32, 4, 8, DIR, false, OUT_REG, WS>(reg, line, lt, tw, swz);
   } else if constexpr (L == 64) {
-    stage<64, 8, 1, DIR, IN_REG, false>(reg, line, lt, tw, swz);
-    stage<64, 8, 8, DIR, false, OUT_REG>(reg, line, lt, tw, swz);
+    stage<64, 8, 1, DIR, IN_REG, false, WS>(reg, line, lt, tw, swz);
+    stage<64, 8, 8, DIR, false, OUT_REG, WS>(reg, line, lt, tw, swz);
   } else if constexpr (L == 128) {
-    stage<128, 16, 1, DIR, IN_REG, false>(reg, line, lt, tw, swz);
-    stage<128, 8, 16, DIR, false, OUT_REG>(reg, line, lt, tw, swz);
+    stage<128, 16, 1, DIR, IN_REG, false, WS>(reg, line, lt, tw, swz);
+    stage<128, 8, 16, DIR, false, OUT_REG, WS>(reg, line, lt, tw, swz);
   } else if constexpr (L == 256) {
-    stage<256, 16, 1, DIR, IN_REG, false>(reg, line, lt, tw, swz);
-    stage<256, 16, 16, DIR, false, OUT_REG>(reg, line, lt, tw, swz);
+    stage<256, 16, 1, DIR, IN_REG, false, WS>(reg, line, lt, tw, swz);
+    stage<256, 16, 16, DIR, false, OUT_REG, WS>(reg, line, lt, tw, swz);
   } else if constexpr (L == 512) {
-    stage<512, 8, 1, DIR, IN_REG, false>(reg, line, lt, tw, swz);
-    stage<512, 8, 8, DIR, false, false>(reg, line, lt, tw, swz);
-    stage<512, 8, 64, DIR, false, OUT_REG>(reg, line, lt, tw, swz);
+    stage<512, 8, 1, DIR, IN_REG, false, WS>(reg, line, lt, tw, swz);
+    stage<512, 8, 8, DIR, false, false, WS>(reg, line, lt, tw, swz);
+    stage<512, 8, 64, DIR, false, OUT_REG, WS>(reg, line, lt, tw, swz);
   } else if constexpr (L == 1024) {
-    stage<1024, 16, 1, DIR, IN_REG, false>(reg, line, lt, tw, swz);
-    stage<1024, 16, 16, DIR, false, false>(reg, line, lt, tw, swz);
-    stage<1024, 4, 256, DIR, false, OUT_REG>(reg, line, lt, tw, swz);
+    stage<1024, 16, 1, DIR, IN_REG, false, WS>(reg, line, lt, tw, swz);
+    stage<1024, 16, 16, DIR, false, false, WS>(reg, line, lt, tw, swz);
+    stage<1024, 4, 256, DIR, false, OUT_REG, WS>(reg, line, lt, tw, swz);
   }
 }
 

@@ -1284,6 +1284,7 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
   constexpr int NCH = MODE == PI_BWD ? 3 : 1;
   constexpr int VK = 16 / KP;  // elements kept per round: the part's rows of the column
   constexpr int64_t CH = (int64_t)H * RES * RES;
+  constexpr bool WS = RES >= 256;  // wavefront-synchronous transforms
   __shared__ __align__(16) cf buf[PL::SLOTS];
   __shared__ cf stw[M];
   __shared__ cf ctw[RES];
@@ -1325,7 +1326,13 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
 #pragma unroll
       for (int v = 0; v < 16; ++v) reg[v] = cscale(reg[v], k2f);
     }
-    fft<RES, +1, true, true>(reg, buf + col * LSC, lt, ctw);
+    // at 256 the transforms synchronise within wavefronts only (a line's
+    // threads are lanes of one wavefront; 16 wavefronts per workgroup): the
+    // tables get a barrier of their own, after the first column loads are in
+    // flight (P45 48.4 -> 47.4 us; at 64 and 128 the workgroup barriers cost
+    // less than the extra ones here)
+    if (WS && rd == 0) __syncthreads();
+    fft<RES, +1, true, true, WS>(reg, buf + col * LSC, lt, ctw);
 #pragma unroll
     for (int w2 = 0; w2 < VK; ++w2) {
       cf x = reg[w2];
@@ -1335,8 +1342,11 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
       keep[rd][w2] = x;
     }
   }
-  // the part's rows into LDS (the last FFT stage ended with a barrier after
-  // its LDS reads): row l = lt + TPL w2, packed column unpacked into k2 = 0, M
+  // the part's rows into LDS, over the columns: every wavefront must be done
+  // reading its columns (the last transform stage ends with a workgroup
+  // barrier unless WS); row l = lt + TPL w2, packed column unpacked into
+  // k2 = 0, M
+  if constexpr (WS) __syncthreads();
 #pragma unroll
   for (int rd = 0; rd < KP; ++rd) {
     const int kk = rd * NCOL + col;
@@ -1390,8 +1400,9 @@ __device__ __forceinline__ void b_plane_inv(const cf* __restrict__ in, float* __
   __syncthreads();
   {
     cf reg[16];
-    fft<M, +1, false, false>(reg, buf + (t / TPR) * LSR, t % TPR, stw, row_swz(M, t / TPR));
+    fft<M, +1, false, false, WS>(reg, buf + (t / TPR) * LSR, t % TPR, stw, row_swz(M, t / TPR));
   }
+  if constexpr (WS) __syncthreads();  // the rows are read below across wavefronts
   // rows now hold real lines, sample n of row l at float slot 2 rpos(l, n/2) + (n&1)
   if constexpr (MODE != PI_BWD) {
     for (int e = t; e < RC * M; e += BLOCK) {
