@@ -746,13 +746,18 @@ __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __res
       reg[v] = lv ? src[lt + TPL * v] : cf{0.0f, 0.0f};
       nxt[v] = lv ? src[CH + lt + TPL * v] : cf{0.0f, 0.0f};
     }
-    fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
+    // the line transforms synchronise within wavefronts only (a line's
+    // threads are lanes of one wavefront, and each touches only its own LDS
+    // line until store_transposed's barrier): the tables get a barrier of
+    // their own, after the line loads are in flight
+    __syncthreads();
+    fft<RES, -1, true, true, true>(reg, rows + l * LS, lt, stw);
 #pragma unroll
     for (int v = 0; v < E; ++v) {
       acc[v] = cscale(reg[v], kappa_odd(lt + TPL * v, RES));
       reg[v] = nxt[v];
     }
-    fft<RES, -1, true, true>(reg, rows + l * LS, lt, stw);
+    fft<RES, -1, true, true, true>(reg, rows + l * LS, lt, stw);
   }
   {
     const float g12 = g1[k1] * g1[k2];
@@ -764,7 +769,7 @@ __device__ __forceinline__ void b_fwd_axis0(const cf* __restrict__ in, cf* __res
       reg[v] = cf{-F * a.y, F * a.x};  // i F sum
     }
   }
-  fft<RES, +1, true, true>(reg, rows + l * LS, lt, stw);
+  fft<RES, +1, true, true, !IN_C>(reg, rows + l * LS, lt, stw);
   store_transposed<RES, TC>(rows, reg, out + (int64_t)k2 * RES + a0, (int64_t)H * RES, l, lt);
 }
 
@@ -799,7 +804,10 @@ __device__ __forceinline__ void b_bwd_axis0(const cf* __restrict__ in, cf* __res
     const cf* src = in + ((int64_t)k2 * RES + k1) * RES;
 #pragma unroll
     for (int v = 0; v < E; ++v) h[v] = src[lt + TPL * v];
-    fft<RES, -1, true, true>(h, rows + l * LS, lt, stw);
+    // wavefront-synchronous line transforms, as in P3: the tables and the
+    // live flags get a barrier of their own
+    __syncthreads();
+    fft<RES, -1, true, true, true>(h, rows + l * LS, lt, stw);
   }
   const float g12 = g1[k1] * g1[k2];
   const float q12 = kappa_of(k1, RES) * kappa_of(k1, RES) + kappa_of(k2, RES) * kappa_of(k2, RES);
@@ -810,10 +818,10 @@ __device__ __forceinline__ void b_bwd_axis0(const cf* __restrict__ in, cf* __res
     const float k0f = kappa_odd(lt + TPL * v, RES);
     reg[v] = cf{k0f * h[v].x, k0f * h[v].y};
   }
-  fft<RES, +1, true, true>(reg, rows + l * LS, lt, stw);
+  fft<RES, +1, true, true, !IN_C>(reg, rows + l * LS, lt, stw);
   store_transposed<RES, TC>(rows, reg, out + (int64_t)k2 * RES + a0, (int64_t)H * RES, l, lt, live);
   __syncthreads();
-  fft<RES, +1, true, true>(h, rows + l * LS, lt, stw);
+  fft<RES, +1, true, true, !IN_C>(h, rows + l * LS, lt, stw);
   store_transposed<RES, TC>(rows, h, out + ((int64_t)RES * H + k2) * RES + a0, (int64_t)H * RES, l, lt, live);
 }
 
