@@ -423,12 +423,13 @@ struct NnSide {
   float* dist;
 };
 
-constexpr int kNnWaves = 4;
+constexpr int kNnWaves = 8;                  // wavefronts per query group
+constexpr int kNnBlock = 64 * kNnWaves;       // threads of a query workgroup
 constexpr int kNnCand = 512;  // tiles tested per pass: the capacity of the candidate list
 
-// One group of kNnTile sorted queries per workgroup, four wavefronts holding
-// the same queries; groups [0, gx) search y from x, the rest x from y.
-// 1. Each wavefront scans one of the four tiles around the reference cell of
+// One group of kNnTile sorted queries per workgroup, kNnWaves wavefronts
+// holding the same queries; groups [0, gx) search y from x, the rest x from y.
+// 1. Each wavefront scans one of the kNnWaves tiles around the reference cell of
 //    the group's first query; the largest best distance of the group then
 //    bounds every neighbour.
 // 2. The tiles whose box lies within that bound of the group's box are listed
@@ -438,9 +439,9 @@ constexpr int kNnCand = 512;  // tiles tested per pass: the capacity of the cand
 //    best; a tile is passed over when no lane's point-to-box bound reaches
 //    that lane's best. A lane's best is the lowest distance any wavefront has
 //    reached for it (published in LDS after every tile).
-// 4. The four results per query are merged (lower distance, then lower
+// 4. The kNnWaves results per query are merged (lower distance, then lower
 //    index).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_nn_query(
+__global__ __launch_bounds__(kNnBlock) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_nn_query(
     const NnSide A, const NnSide Bs, int64_t gx, int cb) {
   __shared__ float4 stg[kNnWaves][kNnTile];
   __shared__ float shb[kNnWaves][kNnTile];
@@ -474,9 +475,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
   const int key = __builtin_amdgcn_readfirstlane(nn_key(q.x, q.y, q.z, cb));
   int64_t t0 = S.rend[key] / kNnTile;
   t0 = t0 > ntr - 1 ? ntr - 1 : t0;
-  int64_t s0 = t0 - 1 > ntr - kNnWaves ? ntr - kNnWaves : t0 - 1;
+  int64_t s0 = t0 - kNnWaves / 2 + 1 > ntr - kNnWaves ? ntr - kNnWaves : t0 - kNnWaves / 2 + 1;
   s0 = s0 < 0 ? 0 : s0;
-  const int64_t s1 = s0 + kNnWaves - 1;  // the start tiles [s0, s1] (fewer when ntr < 4)
+  const int64_t s1 = s0 + kNnWaves - 1;  // the start tiles [s0, s1] (fewer when ntr < kNnWaves)
   float best = inf;
   int bi = 0x7fffffff;
   auto publish = [&]() { __hip_atomic_store(&shb[w][lane], best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); };
@@ -528,7 +529,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     if (threadIdx.x == 0) ncand = 0;
     __syncthreads();
     const int64_t c1 = c0 + kNnCand < ntr ? c0 + kNnCand : ntr;
-    for (int64_t t = c0 + threadIdx.x; t < c1; t += 256) {
+    for (int64_t t = c0 + threadIdx.x; t < c1; t += kNnBlock) {
       if (t >= s0 && t <= s1) continue;
       const float4 lo = S.box[2 * t], hi = S.box[2 * t + 1];
       const float lb = nn_boxbox_d2(ql, qh, lo, hi);
@@ -543,12 +544,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     const int nc = ncand;
     int np2 = 1;
     while (np2 < nc) np2 <<= 1;
-    for (int i = nc + threadIdx.x; i < np2; i += 256) ckey[i] = ~0ull;
+    for (int i = nc + threadIdx.x; i < np2; i += kNnBlock) ckey[i] = ~0ull;
     __syncthreads();
     // ascending bitonic sort of the keys: the nearest boxes first
     for (int k = 2; k <= np2; k <<= 1) {
       for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = threadIdx.x; i < np2; i += 256) {
+        for (int i = threadIdx.x; i < np2; i += kNnBlock) {
           const int l = i ^ j;
           if (l > i) {
             const unsigned long long a = ckey[i], b = ckey[l];
@@ -812,7 +813,7 @@ int run_chamfer(const float* x, int64_t nx, const float* y, int64_t ny, int32_t*
   }
   const NnSide A{sx, nx, sy, by, cnt + nc, ny, nnx, dx};  // samples x against the target y
   const NnSide B{sy, ny, sx, bx, cnt, nx, nny, dy};       // and back
-  hipLaunchKernelGGL(k_nn_query, dim3(tx + ty), dim3(256), 0, s, A, B, tx, cb);
+  hipLaunchKernelGGL(k_nn_query, dim3(tx + ty), dim3(kNnBlock), 0, s, A, B, tx, cb);
   if (loss) hipLaunchKernelGGL(k_chamfer_loss, dim3(1), dim3(1024), 0, s, dx, nx, dy, ny, loss);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
