@@ -72,7 +72,9 @@ def test_sampling_backward_matches_oracle(dev):
     assert e <= 1e-5
 
 
-@pytest.mark.parametrize("nx,ny", [(20000, 20000), (5000, 30000), (257, 1), (40000, 3000)])
+# (40000, 3000): the five-kernel sort (32^3 cells); (300000, 256): 64^3 cells,
+# and the queries of the small cloud list the large one's tiles in ten passes
+@pytest.mark.parametrize("nx,ny", [(20000, 20000), (5000, 30000), (257, 1), (40000, 3000), (300000, 256)])
 def test_chamfer_matches_oracle(dev, nx, ny):
     from paper_2106_03452_amd import optimize as O
     announce(f"chamfer {nx} x {ny} vs oracle")
