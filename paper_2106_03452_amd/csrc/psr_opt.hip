@@ -404,7 +404,7 @@ __device__ __forceinline__ float nn_boxbox_d2(const float3& al, const float3& ah
 }
 
 // orders this wavefront's LDS writes before its own later reads (and the
-// reverse) without a workgroup barrier: the four wavefronts of a group take
+// reverse) without a workgroup barrier: the wavefronts of a query group take
 // different numbers of tiles
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
