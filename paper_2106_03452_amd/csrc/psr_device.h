@@ -114,11 +114,12 @@ __device__ __forceinline__ void for_recs(const Recs<K>& r, const PointRec* __res
 // Records fetched together in the tail of the splat's and gathers' point
 // loops (beyond the first K * BLOCK, so only where a span is dense): none at
 // 256^3 and 512^3, whose row passes have no registers to spare below the
-// 128 that two workgroups per CU allow; eight at 64^3, whose plane passes
-// (128 threads, up to 256 registers) walk the longest lists (64^3 with 10^6
-// points 1.78 -> 1.35 ms); at 128^3 eight cost more in register pressure
-// than they save (the 64-shape batch 33.1k -> 31.3k shapes/s).
-__host__ __device__ constexpr int rec_tail(int res) { return res >= 256 ? 0 : (res == 64 ? 8 : 2); }
+// 128 that two workgroups per CU allow; eight at 64^3 and below, whose
+// plane and row passes (a few hundred workgroups, registers to spare) walk
+// the longest lists (10^6 points: 64^3 1.78 -> 1.35 ms, 32^3 1.53 -> 1.15 ms);
+// at 128^3 eight cost more in register pressure than they save (the
+// 64-shape batch 33.1k -> 31.3k shapes/s).
+__host__ __device__ constexpr int rec_tail(int res) { return res >= 256 ? 0 : (res == 64 || res <= 32 ? 8 : 2); }
 
 // Fixed-point splat. LDS float atomics are several times slower than integer
 // ones on gfx950, and their result depends on the order of the adds, so the
