@@ -570,7 +570,8 @@ def mc_bytes(r: int, nv: int, nt: int, backward: bool = False) -> int:
     """Algorithmic bytes of the Marching Cubes layer: the grid read once and
     the mesh written once (positions, normals, edge ids: 28 B per vertex;
     triangles 12 B), or for the backward the grid read, dL/dchi written and
-    dL/dverts and the normals read (24 B per vertex)."""
+    dL/dverts and the normals read (24 B per vertex). Counted densely: the
+    backward's workgroups without surface write zeros and read nothing."""
     n = r ** 3
     return 8 * n + 24 * nv if backward else 4 * n + 28 * nv + 12 * nt
 

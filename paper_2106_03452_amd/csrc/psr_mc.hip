@@ -43,35 +43,74 @@ __device__ __forceinline__ float3 grad_at(const float* __restrict__ chi, int a, 
 }
 
 // The kMcVpt vertices (j0, j1, j2 .. j2 + 3) of one thread: chi at the corners
-// of their cells, from four rows (j0 + o0, j1 + o1) loaded as float4 plus the
-// value one past the run.
+// of their cells. A thread reads its own run on rows (j0, j1) and (j0 + 1, j1)
+// as float4; the runs on row j1 + 1 are those of thread t + R / kMcVpt, passed
+// through LDS (read from memory only where that thread is in the next
+// workgroup), and the value one past the run is the next lane's first (read
+// from memory only where that lane is in the next wavefront, i.e. rows longer
+// than a wavefront's 256 vertices). Each grid row is so fetched about twice
+// per workgroup instead of eight times.
 template <int R>
 struct Run {
   int j0, j1, j2;
   float v[2][2][kMcVpt + 1];  // [o0][o1][k]: chi(j0 + o0, j1 + o1, j2 + k)
   bool ok0, ok1;              // rows j0 + 1 / j1 + 1 exist
 
-  __device__ __forceinline__ void load(const float* __restrict__ chi, int64_t e, float iso) {
+  // Called by every thread of the workgroup (it holds a workgroup barrier);
+  // live: e is a grid vertex; xs: 2 * kMcThreads float4 of LDS.
+  __device__ __forceinline__ void load(const float* __restrict__ chi, int64_t e, bool live, float iso,
+                                       float4* xs) {
     constexpr int L = __builtin_ctz(R);
+    constexpr int D = R / kMcVpt;  // threads per grid row
+    constexpr int64_t S0 = (int64_t)R * R;
     j2 = (int)(e & (R - 1));
     j1 = (int)((e >> L) & (R - 1));
     j0 = (int)(e >> (2 * L));
-    ok0 = j0 < R - 1;
-    ok1 = j1 < R - 1;
-    const bool ok2 = j2 + kMcVpt < R;
+    ok0 = live && j0 < R - 1;
+    ok1 = live && j1 < R - 1;
+    const int t = threadIdx.x, lane = t & 63;
+    const float4 none = make_float4(iso, iso, iso, iso);
+    auto ld4 = [&](int64_t i) { return *reinterpret_cast<const float4*>(chi + i); };
+    float4 q[2][2];
+    q[0][0] = live ? ld4(e) : none;
+    q[1][0] = ok0 ? ld4(e + S0) : none;
+    xs[t] = q[0][0];
+    xs[kMcThreads + t] = q[1][0];
+    __syncthreads();
+    // thread t + D holds (j0, j1 + 1, j2) whenever j1 + 1 exists
+    if (!ok1) {
+      q[0][1] = none;
+      q[1][1] = none;
+    } else if (t + D < kMcThreads) {
+      q[0][1] = xs[t + D];
+      q[1][1] = xs[kMcThreads + t + D];
+    } else {
+      q[0][1] = ld4(e + R);
+      q[1][1] = ok0 ? ld4(e + S0 + R) : none;
+    }
 #pragma unroll
     for (int o0 = 0; o0 < 2; ++o0)
 #pragma unroll
       for (int o1 = 0; o1 < 2; ++o1) {
-        const bool ok = (!o0 || ok0) && (!o1 || ok1);
-        const int64_t row = e + (int64_t)o0 * R * R + (int64_t)o1 * R;
-        const float4 q = ok ? *reinterpret_cast<const float4*>(chi + row) : make_float4(iso, iso, iso, iso);
-        v[o0][o1][0] = q.x;
-        v[o0][o1][1] = q.y;
-        v[o0][o1][2] = q.z;
-        v[o0][o1][3] = q.w;
-        v[o0][o1][4] = ok && ok2 ? chi[row + kMcVpt] : iso;
+        v[o0][o1][0] = q[o0][o1].x;
+        v[o0][o1][1] = q[o0][o1].y;
+        v[o0][o1][2] = q[o0][o1].z;
+        v[o0][o1][3] = q[o0][o1].w;
+        // the next lane's run continues this one when j2 + kMcVpt < R; otherwise
+        // the value is never read (mask and cell test j2 + k < R - 1)
+        v[o0][o1][kMcVpt] = __shfl_down(q[o0][o1].x, 1, 64);
       }
+    if constexpr (R > 64 * kMcVpt) {
+      if (lane == 63 && live && j2 + kMcVpt < R) {
+#pragma unroll
+        for (int o0 = 0; o0 < 2; ++o0)
+#pragma unroll
+          for (int o1 = 0; o1 < 2; ++o1) {
+            const bool ok = (!o0 || ok0) && (!o1 || ok1);
+            v[o0][o1][kMcVpt] = ok ? chi[e + o0 * S0 + o1 * R + kMcVpt] : iso;
+          }
+      }
+    }
   }
   // crossing mask of the three edges owned by vertex j2 + k
   __device__ __forceinline__ int mask(int k, float iso) const {
@@ -120,21 +159,36 @@ __device__ __forceinline__ int2 block_scan2(int2 v, int2* wtot, int2& total) {
 
 template <int R>
 __global__ __launch_bounds__(kMcThreads) void k_mc_count(const float* __restrict__ chi, float iso, McState st) {
-  __shared__ int2 wtot[kMcThreads / 64];
+  static_assert(kMcThreads == 256, "one table entry per thread");
+  __shared__ float4 xs[2 * kMcThreads];
+  __shared__ int8_t ntri[256];  // triangles per cell case, read from LDS rather than from memory
+  __shared__ int wsum[kMcThreads / 64];
+  ntri[threadIdx.x] = kTable.ntri[threadIdx.x];  // visible after the barrier in load
   const int64_t e = ((int64_t)blockIdx.x * kMcThreads + threadIdx.x) * kMcVpt;
+  const bool live = e < (int64_t)R * R * R;
   int nv = 0, nt = 0;
-  if (e < (int64_t)R * R * R) {
-    Run<R> q;
-    q.load(chi, e, iso);
+  Run<R> q;
+  q.load(chi, e, live, iso, xs);
+  if (live) {
 #pragma unroll
     for (int k = 0; k < kMcVpt; ++k) {
       nv += __popc(q.mask(k, iso));
-      nt += kTable.ntri[q.cell(k, iso)];
+      nt += ntri[q.cell(k, iso)];
     }
   }
-  int2 tot;
-  block_scan2<kMcThreads>(make_int2(nv, nt), wtot, tot);
+  // workgroup totals, both counters in one word: at most 3 * 1024 crossing
+  // edges and kMaxTri * 1024 triangles per workgroup, each below 2^16
+  static_assert(3 * kMcBlock < (1 << 16) && kMaxTri * kMcBlock < (1 << 15), "packed counters");
+  int sum = nv | (nt << 16);
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) sum += __shfl_down(sum, d, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = sum;
+  __syncthreads();
   if (threadIdx.x == 0) {
+    int w = 0;
+#pragma unroll
+    for (int i = 0; i < kMcThreads / 64; ++i) w += wsum[i];
+    const int2 tot = make_int2(w & 0xffff, w >> 16);
     st.blk[blockIdx.x] = tot;
     st.cnt[blockIdx.x] = tot;
   }
@@ -187,15 +241,18 @@ __global__ __launch_bounds__(kMcThreads) void k_mc_emit(const float* __restrict_
   }
   const int64_t e = ((int64_t)blockIdx.x * kMcThreads + threadIdx.x) * kMcVpt;
   const bool live = e < (int64_t)R * R * R;
+  __shared__ float4 xs[2 * kMcThreads];
+  __shared__ int8_t ntri[256];  // triangles per cell case (visible after the barrier in load)
+  ntri[threadIdx.x] = kTable.ntri[threadIdx.x];
   Run<R> q;
   int m[kMcVpt], cs[kMcVpt], nv = 0, nt = 0;
-  if (live) q.load(chi, e, iso);
+  q.load(chi, e, live, iso, xs);
 #pragma unroll
   for (int k = 0; k < kMcVpt; ++k) {
     m[k] = live ? q.mask(k, iso) : 0;
     cs[k] = live ? q.cell(k, iso) : 0;
     nv += __popc(m[k]);
-    nt += kTable.ntri[cs[k]];
+    nt += ntri[cs[k]];
   }
   int2 tot;
   const int2 incl = block_scan2<kMcThreads>(make_int2(nv, nt), wtot, tot);
@@ -277,7 +334,7 @@ __global__ __launch_bounds__(kMcThreads) void k_mc_emit(const float* __restrict_
     int cell = 0, i = x - pt[o];
 #pragma unroll
     for (int kk = 0; kk < kMcVpt - 1; ++kk) {
-      const int n = kTable.ntri[(co >> (8 * kk)) & 255];
+      const int n = ntri[(co >> (8 * kk)) & 255];
       if (cell == kk && i >= n) {
         i -= n;
         cell = kk + 1;
@@ -310,44 +367,75 @@ __global__ __launch_bounds__(256) void k_mc_link(McState st, McOut out) {
 }
 
 // one thread per kMcVpt consecutive grid vertices; each sums, in a fixed
-// order, the contributions of the up to six crossing edges that meet there
+// order, the contributions of the up to six crossing edges that meet there.
+// A workgroup none of whose vertices, nor their lower neighbours along the
+// three axes, owns a crossing edge (the forward's per-workgroup counts tell)
+// writes zeros without reading chi. Elsewhere rows j1 -/+ 1 come from the
+// threads R / kMcVpt before and after through LDS, and chi at j2 - 1 and
+// j2 + kMcVpt from the neighbouring lanes.
 template <int R>
 __global__ __launch_bounds__(kMcThreads) void k_mc_backward(const float* __restrict__ chi, float iso, McState st,
                                                             const float* __restrict__ normals,
                                                             const float* __restrict__ dverts, int64_t nverts,
                                                             float* __restrict__ dchi) {
   constexpr int L = __builtin_ctz(R);
-  const int64_t e = ((int64_t)blockIdx.x * kMcThreads + threadIdx.x) * kMcVpt;
-  if (e >= (int64_t)R * R * R) return;
+  constexpr int D = R / kMcVpt;  // threads per grid row
+  static_assert(R <= kMcBlock, "a row and its predecessor lie in this and the previous workgroup");
+  __shared__ float4 xs[kMcThreads];
+  const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+  const int64_t e = ((int64_t)b * kMcThreads + tid) * kMcVpt;
+  const bool live = e < (int64_t)R * R * R;
+  const int64_t s0 = (int64_t)R * R, s1 = R;
   if (st.hdr->res != R || st.hdr->iso != iso) {
     // the state comes from another grid size or level: no valid vertex map
     const float nan = __int_as_float(0x7fc00000);
-    *reinterpret_cast<float4*>(dchi + e) = make_float4(nan, nan, nan, nan);
+    if (live) *reinterpret_cast<float4*>(dchi + e) = make_float4(nan, nan, nan, nan);
     return;
   }
+  {
+    // owners of the edges that end in this workgroup: its own vertices, e - 1
+    // and e - R (this workgroup or the previous one), e - R^2 (the workgroup
+    // R^2 vertices back, R^2 being a multiple of the workgroup's vertices or
+    // below them)
+    const int64_t eb = (int64_t)b * kMcBlock;
+    const bool any = st.cnt[b].x != 0 || (b > 0 && st.cnt[b - 1].x != 0) ||
+                     (eb >= s0 && st.cnt[(eb - s0) / kMcBlock].x != 0);
+    if (!any) {
+      if (live) *reinterpret_cast<float4*>(dchi + e) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      return;
+    }
+  }
   const int j2 = (int)(e & (R - 1)), j1 = (int)((e >> L) & (R - 1)), j0 = (int)(e >> (2 * L));
-  const int64_t s0 = (int64_t)R * R, s1 = R;
   // chi along the run (j2 - 1 .. j2 + 4) and on the four neighbouring rows
   float c[kMcVpt + 2], xm[kMcVpt], xp[kMcVpt], ym[kMcVpt], yp[kMcVpt];
   {
-    const float4 q = *reinterpret_cast<const float4*>(chi + e);
+    const float4 none = make_float4(iso, iso, iso, iso);
+    auto ld4 = [&](int64_t i) { return *reinterpret_cast<const float4*>(chi + i); };
+    const float4 q = live ? ld4(e) : none;
+    const float4 rxm = live && j0 > 0 ? ld4(e - s0) : none;
+    const float4 rxp = live && j0 < R - 1 ? ld4(e + s0) : none;
+    xs[tid] = q;
+    __syncthreads();
+    // threads tid -/+ D hold (j0, j1 -/+ 1, j2) whenever that row exists
+    const float4 rym = !live || j1 == 0 ? none : (tid >= D ? xs[tid - D] : ld4(e - s1));
+    const float4 ryp = !live || j1 == R - 1 ? none : (tid + D < kMcThreads ? xs[tid + D] : ld4(e + s1));
+    const float pw = __shfl_up(q.w, 1, 64), nx = __shfl_down(q.x, 1, 64);
+    c[0] = live && j2 > 0 ? (lane > 0 ? pw : chi[e - 1]) : iso;
     c[1] = q.x;
     c[2] = q.y;
     c[3] = q.z;
     c[4] = q.w;
-    c[0] = j2 > 0 ? chi[e - 1] : iso;
-    c[5] = j2 + kMcVpt < R ? chi[e + kMcVpt] : iso;
-    auto row = [&](bool ok, int64_t off, float* d) {
-      const float4 r = ok ? *reinterpret_cast<const float4*>(chi + e + off) : make_float4(iso, iso, iso, iso);
+    c[5] = live && j2 + kMcVpt < R ? (lane < 63 ? nx : chi[e + kMcVpt]) : iso;
+    auto put = [](const float4& r, float* d) {
       d[0] = r.x;
       d[1] = r.y;
       d[2] = r.z;
       d[3] = r.w;
     };
-    row(j0 > 0, -s0, xm);
-    row(j0 < R - 1, s0, xp);
-    row(j1 > 0, -s1, ym);
-    row(j1 < R - 1, s1, yp);
+    put(rxm, xm);
+    put(rxp, xp);
+    put(rym, ym);
+    put(ryp, yp);
   }
   auto gv = [&](int64_t owner, int a) {
     const uint32_t vb = st.vbase[owner];
@@ -356,6 +444,7 @@ __global__ __launch_bounds__(kMcThreads) void k_mc_backward(const float* __restr
     return -(dverts[3 * v] * normals[3 * v] + dverts[3 * v + 1] * normals[3 * v + 1] +
              dverts[3 * v + 2] * normals[3 * v + 2]);
   };
+  if (!live) return;
   float out[kMcVpt];
 #pragma unroll
   for (int k = 0; k < kMcVpt; ++k) {

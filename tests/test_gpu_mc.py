@@ -81,7 +81,8 @@ def test_capacity_overflow_reruns(dev):
     assert m.verts.shape[0] == len(ref["verts"]) > 100
 
 
-@pytest.mark.parametrize("kind,r", [("sphere", 32), ("noise", 32), ("torus", 128)])
+@pytest.mark.parametrize("kind,r", [("sphere", 8), ("noise", 16), ("sphere", 32), ("noise", 32), ("torus", 128),
+                                    ("sphere", 256), ("torus", 512)])
 def test_backward_matches_oracle(dev, kind, r):
     from paper_2106_03452_amd import mesh as M
     announce(f"marching cubes backward {kind} {r}^3")
