@@ -51,8 +51,8 @@ def _compare(chi32, dev, iso=0.0, capacity=None):
     return m, ref, e_p, e_n
 
 
-@pytest.mark.parametrize("kind,r", [("sphere", 16), ("sphere", 64), ("torus", 128), ("noise", 32), ("sphere", 256),
-                                    ("torus", 512)])
+@pytest.mark.parametrize("kind,r", [("sphere", 8), ("noise", 8), ("sphere", 16), ("sphere", 64), ("torus", 128),
+                                    ("noise", 32), ("sphere", 256), ("torus", 512)])
 def test_mesh_matches_oracle(dev, kind, r):
     announce(f"marching cubes {kind} {r}^3")
     m, ref, e_p, e_n = _compare(_field(kind, r), dev)
